@@ -1,0 +1,367 @@
+/*
+ * CPU oracle for the GMM rANS entropy coder — TEST INFRASTRUCTURE ONLY.
+ * (Loaded by the tests, the smoke check and the benchmark's CPU baseline;
+ * never by the GPU library or its Python binding.)
+ *
+ * What it computes, and where the paper defines it (FlashGMM, Murai, Lin,
+ * Katto, arXiv 2509.18815):
+ *   - Sec. II-A, Eq. (1) and Eq. (2): a latent element's probability model
+ *     is a K-component Gaussian mixture, and the mass of the integer symbol
+ *     y is the mixture CDF difference across the half-integer boundaries
+ *     y-1/2 and y+1/2.
+ *   - Sec. II-C, Eqs. (4)-(6): the classic coder builds, per element, the
+ *     table T_i of cumulative masses over the whole alphabet; by telescoping,
+ *     its j-th entry is the mixture CDF at one boundary. This oracle builds
+ *     that column for every element (O(K |y| |Y|)) and uses it for encode
+ *     (lookup) and decode (linear search of the column).
+ *   - Sec. II-B, Eq. (3): the rANS state map C(s,x) = m floor(x/l_s) + b_s +
+ *     mod(x, l_s) with m = 2^P, l_s = the symbol's frequency, b_s = its
+ *     cumulative frequency.
+ *   - Sec. III-B: the Gaussian CDF is replaced by a closed-form approximation:
+ *     the Abramowitz & Stegun 26.2.17 polynomial (default) or the logistic
+ *     function 1/(1+exp(-1.702 x)).
+ * The paper fixes no float format, rANS word size, stream layout or CDF
+ * quantization; the readings taken here (binary32 with a fixed operation
+ * order, 32-bit state with 16-bit renormalisation, round-robin interleaved
+ * streams, c_j = j + floor(F (M-N))) are the written contract that the GPU
+ * library also implements, independently.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fno-fast-math -fopenmp (no FMA
+ * contraction: every fused multiply-add below is an explicit fmaf).
+ */
+#include "gmm_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ---- constants: each is the binary32 value nearest the stated real ---- */
+/* A&S 26.2.17 (Handbook of Mathematical Functions, Sec. 26.2.17). */
+static const float AS_P = 0x1.da6712p-3f;  /* 0.2316419 */
+static const float AS_B1 = 0x1.470bf4p-2f; /* 0.319381530 */
+static const float AS_B2 = -0x1.6d1f0ep-2f; /* -0.356563782 */
+static const float AS_B3 = 0x1.c80ef0p+0f; /* 1.781477937 */
+static const float AS_B4 = -0x1.d23dd4p+0f; /* -1.821255978 */
+static const float AS_B5 = 0x1.548cdep+0f; /* 1.330274429 */
+static const float INV_SQRT_2PI = 0x1.988454p-2f; /* 1/sqrt(2 pi) */
+/* logistic approximation slope (paper Sec. III-B, third candidate) */
+static const float LOGISTIC_K = 0x1.b3b646p+0f; /* 1.702 */
+/* exp~: Cody & Waite argument reduction, ln 2 split in two parts. */
+static const float LOG2E = 0x1.715476p+0f;   /* 1/ln 2 */
+static const float LN2_HI = 0x1.62e4p-1f;    /* ln 2 truncated to 16 significant bits */
+static const float LN2_LO = 0x1.7f7d1cp-20f; /* ln 2 - LN2_HI */
+static const float INV_FACT3 = 0x1.555556p-3f;  /* 1/3! */
+static const float INV_FACT4 = 0x1.555556p-5f;  /* 1/4! */
+static const float INV_FACT5 = 0x1.111112p-7f;  /* 1/5! */
+static const float INV_FACT6 = 0x1.6c16c2p-10f; /* 1/6! */
+static const float INV_FACT7 = 0x1.a01a02p-13f; /* 1/7! */
+
+/* exp(g) for g in [-40.5, 0]: n = rint(g / ln 2), r = g - n ln 2 (two fused
+ * steps, exact high part), then the Taylor polynomial sum_{k<=7} r^k / k!
+ * by Horner, scaled by 2^n. */
+float gmm_oracle_exp(float g) {
+  float n = rintf(g * LOG2E);
+  float r = fmaf(-n, LN2_HI, g);
+  r = fmaf(-n, LN2_LO, r);
+  float p = INV_FACT7;
+  p = fmaf(p, r, INV_FACT6);
+  p = fmaf(p, r, INV_FACT5);
+  p = fmaf(p, r, INV_FACT4);
+  p = fmaf(p, r, INV_FACT3);
+  p = fmaf(p, r, 0.5f);
+  p = fmaf(p, r, 1.0f);
+  p = fmaf(p, r, 1.0f);
+  return ldexpf(p, (int)n);
+}
+
+/* Upper tail 1 - Phi(a) for a >= 0 by A&S 26.2.17:
+ * Z(a) * (b1 t + ... + b5 t^5), t = 1/(1 + p a), Z the standard normal pdf. */
+static float tail_as(float a) {
+  float u = fmaf(AS_P, a, 1.0f);
+  float t = 1.0f / u;
+  float q = fmaf(AS_B5, t, AS_B4);
+  q = fmaf(q, t, AS_B3);
+  q = fmaf(q, t, AS_B2);
+  q = fmaf(q, t, AS_B1);
+  q = q * t;
+  float m = a * a;
+  float g = m * -0.5f;
+  float e = gmm_oracle_exp(g);
+  float zf = INV_SQRT_2PI * e;
+  return zf * q;
+}
+
+/* Upper tail of the logistic approximation: 1 - 1/(1+exp(-k a)) =
+ * e/(1+e) with e = exp(-k a). */
+static float tail_logistic(float a) {
+  float g = a * -LOGISTIC_K;
+  float e = gmm_oracle_exp(g);
+  return e / (1.0f + e);
+}
+
+/* Phi~(z): clamp z to [-9, 9]; Phi(-a) = tail(a) and Phi(a) = 1 - tail(a).
+ * The float A&S tail slightly exceeds 1/2 for tiny a (its coefficients sum
+ * to just over sqrt(pi/2) after rounding), which would make Phi~ step down
+ * across z = 0; capping the tail at 1/2 keeps Phi~ non-decreasing there. */
+float gmm_oracle_phi(float z, int32_t kind) {
+  z = fminf(fmaxf(z, -9.0f), 9.0f);
+  float a = fabsf(z);
+  float tail = (kind == 1) ? tail_logistic(a) : tail_as(a);
+  tail = fminf(tail, 0.5f);
+  return (z < 0.0f) ? tail : 1.0f - tail;
+}
+
+void gmm_oracle_phi_batch(const float* z, float* out, int64_t n, int32_t kind) {
+  for (int64_t i = 0; i < n; ++i) out[i] = gmm_oracle_phi(z[i], kind);
+}
+
+void gmm_oracle_exp_batch(const float* g, float* out, int64_t n) {
+  for (int64_t i = 0; i < n; ++i) out[i] = gmm_oracle_exp(g[i]);
+}
+
+int32_t gmm_oracle_num_threads(void) {
+#ifdef _OPENMP
+  return (int32_t)omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* ---------------- configuration checks ---------------- */
+static int check_cfg(const gmm_oracle_cfg* c, int64_t n) {
+  if (!c || n < 0) return ORC_EINVAL;
+  if (c->K < 1 || c->K > 8) return ORC_EINVAL;
+  if (c->precision < 2 || c->precision > 16) return ORC_EINVAL;
+  if (c->num_streams < 1) return ORC_EINVAL;
+  if (c->cdf_kind != 0 && c->cdf_kind != 1) return ORC_EINVAL;
+  if (c->lo < -(1 << 22) || c->hi > (1 << 22) || c->hi <= c->lo) return ORC_EINVAL;
+  int64_t N = (int64_t)c->hi - c->lo + 1;
+  int64_t M = (int64_t)1 << c->precision;
+  if (N < 2 || N > M / 2) return ORC_EINVAL;
+  return ORC_OK;
+}
+
+/* One element's parameters after the per-element clamps: scale to
+ * [2^-10, 2^10] and its reciprocal, weights below 2^-60 to zero. */
+typedef struct {
+  float w[8], mu[8], r[8];
+} elem_params;
+
+static void load_elem(const gmm_oracle_cfg* c, int64_t n, int64_t i, const float* w,
+                      const float* mu, const float* sig, elem_params* e) {
+  for (int k = 0; k < c->K; ++k) {
+    float s = fminf(fmaxf(sig[(int64_t)k * n + i], 0x1p-10f), 0x1p10f);
+    e->r[k] = 1.0f / s;
+    float wk = w[(int64_t)k * n + i];
+    e->w[k] = (wk < 0x1p-60f) ? 0.0f : wk;
+    e->mu[k] = mu[(int64_t)k * n + i];
+  }
+}
+
+/* Mixture CDF sum_k w_k Phi~((b - mu_k)/sigma_k) at boundary j, components
+ * accumulated in order with fused multiply-adds, clamped to 1. */
+static float mixture_F(const gmm_oracle_cfg* c, const elem_params* e, int64_t j) {
+  float b = (float)(c->lo + j) - 0.5f;
+  float F = 0.0f;
+  for (int k = 0; k < c->K; ++k) {
+    float z = (b - e->mu[k]) * e->r[k];
+    F = fmaf(e->w[k], gmm_oracle_phi(z, c->cdf_kind), F);
+  }
+  return fminf(F, 1.0f);
+}
+
+/* Quantized CDF column: c_0 = 0, c_N = M, and for 0 < j < N
+ * c_j = j + floor(F_j (M - N)), which is strictly increasing (every symbol
+ * keeps frequency >= 1) because F_j does not decrease with j. */
+static void build_column(const gmm_oracle_cfg* c, const elem_params* e, uint32_t* col) {
+  int64_t N = (int64_t)c->hi - c->lo + 1;
+  uint32_t M = 1u << c->precision;
+  float span = (float)(M - (uint32_t)N);
+  col[0] = 0;
+  for (int64_t j = 1; j < N; ++j) {
+    float F = mixture_F(c, e, j);
+    col[j] = (uint32_t)j + (uint32_t)floorf(F * span);
+  }
+  col[N] = M;
+}
+
+int gmm_oracle_F_table(const gmm_oracle_cfg* c, int64_t n, const float* w, const float* mu,
+                       const float* sig, float* out) {
+  int st = check_cfg(c, n);
+  if (st) return st;
+  int64_t N = (int64_t)c->hi - c->lo + 1;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    elem_params e;
+    load_elem(c, n, i, w, mu, sig, &e);
+    for (int64_t j = 0; j <= N; ++j) out[i * (N + 1) + j] = mixture_F(c, &e, j);
+  }
+  return ORC_OK;
+}
+
+int gmm_oracle_cdf_table(const gmm_oracle_cfg* c, int64_t n, const float* w, const float* mu,
+                         const float* sig, uint32_t* out) {
+  int st = check_cfg(c, n);
+  if (st) return st;
+  int64_t N = (int64_t)c->hi - c->lo + 1;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    elem_params e;
+    load_elem(c, n, i, w, mu, sig, &e);
+    build_column(c, &e, out + i * (N + 1));
+  }
+  return ORC_OK;
+}
+
+/* Element i belongs to stream i mod S at position i div S. */
+static int64_t stream_len(int64_t n, int64_t S, int64_t s) {
+  return (s < n) ? (n - 1 - s) / S + 1 : 0;
+}
+
+int gmm_oracle_inverse(const gmm_oracle_cfg* c, int64_t n, const float* w, const float* mu,
+                       const float* sig, const uint32_t* slot, int32_t* j_out) {
+  int st = check_cfg(c, n);
+  if (st) return st;
+  int64_t N = (int64_t)c->hi - c->lo + 1;
+  uint32_t M = 1u << c->precision;
+  for (int64_t i = 0; i < n; ++i)
+    if (slot[i] >= M) return ORC_EINVAL;
+#pragma omp parallel
+  {
+    uint32_t* col = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(N + 1));
+#pragma omp for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+      elem_params e;
+      load_elem(c, n, i, w, mu, sig, &e);
+      build_column(c, &e, col);
+      int64_t j = 0;
+      while (col[j + 1] <= slot[i]) ++j;
+      j_out[i] = (int32_t)j;
+    }
+    free(col);
+  }
+  return ORC_OK;
+}
+
+int gmm_oracle_encode(const gmm_oracle_cfg* c, int64_t n, const int32_t* sym, const float* w,
+                      const float* mu, const float* sig, uint16_t* bitstream,
+                      int64_t capacity_words, int64_t* offsets) {
+  int st = check_cfg(c, n);
+  if (st) return st;
+  for (int64_t i = 0; i < n; ++i)
+    if (sym[i] < c->lo || sym[i] > c->hi) return ORC_ERANGE;
+  const int64_t S = c->num_streams;
+  const int64_t N = (int64_t)c->hi - c->lo + 1;
+  const int P = c->precision;
+
+  /* Words of stream s are kept in emission order in tmp[base[s] ...]. */
+  int64_t* base = (int64_t*)malloc(sizeof(int64_t) * (size_t)(S + 1));
+  int64_t* count = (int64_t*)malloc(sizeof(int64_t) * (size_t)S);
+  uint32_t* xfin = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)S);
+  base[0] = 0;
+  for (int64_t s = 0; s < S; ++s) base[s + 1] = base[s] + stream_len(n, S, s);
+  uint16_t* tmp = (uint16_t*)malloc(sizeof(uint16_t) * (size_t)(n > 0 ? n : 1));
+
+#pragma omp parallel
+  {
+    uint32_t* col = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(N + 1));
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t s = 0; s < S; ++s) {
+      uint32_t x = 1u << 16;
+      int64_t cnt = 0;
+      /* rANS codes in reverse so that the decoder reads forward. */
+      for (int64_t p = stream_len(n, S, s) - 1; p >= 0; --p) {
+        int64_t i = s + p * S;
+        elem_params e;
+        load_elem(c, n, i, w, mu, sig, &e);
+        build_column(c, &e, col);
+        int64_t j = sym[i] - c->lo;
+        uint32_t cj = col[j];
+        uint32_t f = col[j + 1] - col[j];
+        /* keep x below f 2^(32-P) so the update stays in [2^16, 2^32) */
+        if (x >= (f << (32 - P))) {
+          tmp[base[s] + cnt++] = (uint16_t)(x & 0xFFFFu);
+          x >>= 16;
+        }
+        x = ((x / f) << P) + (x % f) + cj; /* Eq. (3) */
+      }
+      xfin[s] = x;
+      count[s] = cnt;
+    }
+    free(col);
+  }
+
+  offsets[0] = 0;
+  for (int64_t s = 0; s < S; ++s) offsets[s + 1] = offsets[s] + 2 + count[s];
+  if (offsets[S] > capacity_words) {
+    st = ORC_ENOSPC;
+  } else {
+    for (int64_t s = 0; s < S; ++s) {
+      uint16_t* seg = bitstream + offsets[s];
+      seg[0] = (uint16_t)(xfin[s] & 0xFFFFu);
+      seg[1] = (uint16_t)(xfin[s] >> 16);
+      for (int64_t t = 0; t < count[s]; ++t) seg[2 + t] = tmp[base[s] + count[s] - 1 - t];
+    }
+  }
+  free(base);
+  free(count);
+  free(xfin);
+  free(tmp);
+  return st;
+}
+
+int gmm_oracle_decode(const gmm_oracle_cfg* c, int64_t n, const uint16_t* bitstream,
+                      int64_t total_words, const int64_t* offsets, const float* w,
+                      const float* mu, const float* sig, int32_t* sym) {
+  int st = check_cfg(c, n);
+  if (st) return st;
+  if (total_words < 0) return ORC_EINVAL;
+  const int64_t S = c->num_streams;
+  const int64_t N = (int64_t)c->hi - c->lo + 1;
+  const int P = c->precision;
+  const uint32_t M = 1u << P;
+  int corrupt = 0;
+
+#pragma omp parallel reduction(| : corrupt)
+  {
+    uint32_t* col = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(N + 1));
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t s = 0; s < S; ++s) {
+      int64_t ns = stream_len(n, S, s);
+      int64_t a = offsets[s], b = offsets[s + 1];
+      if (a < 0 || b < a + 2 || b > total_words) {
+        for (int64_t p = 0; p < ns; ++p) sym[s + p * S] = c->lo;
+        corrupt = 1;
+        continue;
+      }
+      uint32_t x = (uint32_t)bitstream[a] | ((uint32_t)bitstream[a + 1] << 16);
+      int64_t ptr = a + 2;
+      int bad = (x < (1u << 16));
+      for (int64_t p = 0; p < ns; ++p) {
+        int64_t i = s + p * S;
+        elem_params e;
+        load_elem(c, n, i, w, mu, sig, &e);
+        build_column(c, &e, col);
+        uint32_t slot = x & (M - 1);
+        int64_t j = 0;
+        while (col[j + 1] <= slot) ++j; /* linear search of the column */
+        sym[i] = (int32_t)(c->lo + j);
+        uint32_t f = col[j + 1] - col[j];
+        x = f * (x >> P) + slot - col[j];
+        if (x < (1u << 16)) {
+          uint32_t word = 0;
+          if (ptr < b) word = bitstream[ptr++];
+          else bad = 1;
+          x = (x << 16) | word;
+        }
+      }
+      if (x != (1u << 16) || ptr != b) bad = 1;
+      if (bad) corrupt = 1;
+    }
+    free(col);
+  }
+  return corrupt ? ORC_ECORRUPT : ORC_OK;
+}

@@ -1,0 +1,215 @@
+"""Pins of the oracle's CDF arithmetic against what the paper and the
+mathematics fix (no GPU).
+
+- Phi~ against the Gaussian CDF definition (FlashGMM Sec. III-B, the integral
+  definition of Phi) evaluated by scipy in binary64, within the A&S 26.2.17
+  error bound the paper quotes (7.5e-8, Sec. V) plus float evaluation error.
+- exp~ against binary64 exp.
+- the mixture CDF of Eq. (2) against a binary64 evaluation: 2e-6 absolute.
+- monotonicity of the quantized CDF: exhaustive float scan + hazard bound.
+- K = 1 reduces to the single-Gaussian bin model (Sec. II-A).
+- hand-derived columns from printed normal-table values (tests/golden).
+"""
+import ctypes
+import os
+import struct
+import subprocess
+
+import numpy as np
+import pytest
+from scipy.special import ndtr
+
+from conftest import ROOT, read_golden
+from paper_2509_18815_amd import synth
+
+AS_BOUND = 7.5e-8            # A&S 26.2.17 maximum error
+F32_EVAL = 2.0 ** -22        # float evaluation allowance (4 ulp at 1/2)
+
+
+def f32_grid(lo, hi, n, rng=None):
+    g = np.linspace(lo, hi, n).astype(np.float32)
+    if rng is not None:
+        g = np.concatenate([g, rng.uniform(lo, hi, n).astype(np.float32)])
+    return g
+
+
+def test_phi_as_matches_gaussian_cdf(orc):
+    rng = np.random.default_rng(11)
+    z = f32_grid(-12.0, 12.0, 1_000_001, rng)
+    z = np.concatenate([z, np.float32([0.0, -0.0, 1e-30, -1e-30, 9.0, -9.0, 8.999999, -8.999999])])
+    p = orc.phi(z, 0).astype(np.float64)
+    err = np.abs(p - ndtr(z.astype(np.float64)))
+    assert err.max() <= AS_BOUND + F32_EVAL, err.max()
+    assert p.min() >= 0.0 and p.max() <= 1.0
+
+
+def test_phi_logistic_matches_definition(orc):
+    z = f32_grid(-12.0, 12.0, 400_001)
+    p = orc.phi(z, 1).astype(np.float64)
+    zc = np.clip(z.astype(np.float64), -9.0, 9.0)
+    ref = 1.0 / (1.0 + np.exp(-float(np.float32(1.702)) * zc))
+    assert np.abs(p - ref).max() <= 4 * F32_EVAL
+
+
+def test_phi_reflection_and_clamp(orc):
+    a = f32_grid(1e-3, 12.0, 100_001)
+    for kind in (0, 1):
+        lo = orc.phi(-a, kind).astype(np.float64)
+        hi = orc.phi(a, kind).astype(np.float64)
+        # Phi(-a) + Phi(a) = 1 up to float rounding of 1 - tail
+        assert np.abs(lo + hi - 1.0).max() <= 2.0 ** -24
+        # beyond |z| = 9 the value is the clamped one
+        big = a > 9.0
+        assert np.all(lo[big] == orc.phi(np.float32([-9.0]), kind)[0])
+
+
+def test_phi_non_decreasing_on_sorted_floats(orc):
+    """Phi~ never steps down: on every float near 0 (where the two
+    branches meet) and on a dense sorted grid over the whole range."""
+    bits = np.arange(0, 1 << 20, dtype=np.uint32)
+    tiny = bits.view(np.float32)                      # 0 and the smallest floats
+    near = np.concatenate([-tiny[::-1], tiny, np.float32([1e-7, 1e-6, 1e-3])])
+    grid = np.sort(np.concatenate([near, f32_grid(-10.0, 10.0, 2_000_001)]))
+    for kind in (0, 1):
+        p = orc.phi(grid, kind)
+        assert np.all(np.diff(p.astype(np.float64)) >= 0.0)
+
+
+def test_exp_matches_binary64(orc):
+    rng = np.random.default_rng(12)
+    g = f32_grid(-40.5, 0.0, 1_000_001, rng)
+    e = orc.exp(g).astype(np.float64)
+    ref = np.exp(g.astype(np.float64))
+    rel = np.abs(e - ref) / ref
+    assert rel.max() <= 2.0 ** -23, rel.max()
+    assert orc.exp(np.float32([0.0]))[0] == 1.0
+
+
+@pytest.mark.parametrize("K,lo,hi,s_logit,s_mu,smax,n", [
+    (3, -128, 127, 1.0, 2.0, 20.0, 3000),
+    (3, -255, 255, 1.0, 2.0, 20.0, 2000),
+    (5, -511, 511, 1.5, 4.0, 40.0, 1000),
+    (1, -64, 63, 1.0, 2.0, 20.0, 3000),
+])
+def test_mixture_cdf_within_2e6_of_binary64(orc, K, lo, hi, s_logit, s_mu, smax, n):
+    rng = np.random.default_rng(100 + K + hi)
+    w, mu, sig = synth.random_params(rng, n, K, s_logit, s_mu, smax)
+    cfg = orc.make_cfg(K, lo, hi, 16, 1)
+    F = orc.F_table(cfg, w, mu, sig).astype(np.float64)          # [n][N+1]
+    b = np.arange(lo, hi + 2, dtype=np.float64) - 0.5            # N+1 boundaries
+    ref = np.zeros_like(F)
+    for k in range(K):
+        ref += w[k][:, None].astype(np.float64) * ndtr(
+            (b[None, :] - mu[k][:, None].astype(np.float64)) / sig[k][:, None].astype(np.float64))
+    err = np.abs(F - np.minimum(ref, 1.0))
+    assert err.max() <= 2e-6, err.max()
+
+
+def _lemma_lib():
+    so = os.path.join("/tmp", f"lemma_scan_{os.getpid()}.so")
+    subprocess.run(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared", "-o", so,
+                    os.path.join(ROOT, "tests", "lemma_scan.c"),
+                    os.path.join(ROOT, "oracle", "liboracle.so"), "-lm"], check=True)
+    return ctypes.CDLL(so)
+
+
+def _hazard_min(kind, n=2_000_001):
+    """min over [0, 9] of -d ln tail(a)/da for the binary64 approximant with
+    the binary32 constants (analytic derivative)."""
+    a = np.linspace(0.0, 9.0, n)
+    if kind == 1:
+        k = float(np.float32(1.702))
+        return float((k / (1.0 + np.exp(-k * a))).min()), a[1] - a[0]
+    p = float(np.float32(0.2316419))
+    b = [float(np.float32(v)) for v in (0.319381530, -0.356563782, 1.781477937,
+                                        -1.821255978, 1.330274429)]
+    t = 1.0 / (1.0 + p * a)
+    q = sum(bi * t ** (i + 1) for i, bi in enumerate(b))
+    dq = sum((i + 1) * bi * t ** i for i, bi in enumerate(b))
+    h = a + p * t * t * dq / q
+    return float(h.min()), a[1] - a[0]
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_monotonicity_lemma_exhaustive(orc, kind):
+    """Every float a in [0, 9]: the float tail's relative error E against the
+    binary64 approximant, with hazard h, gives exp(-h d)(1+E)/(1-E) < 1 for
+    the smallest boundary step d = 2^-11 in z, so the float tail strictly
+    decreases across steps; tail <= 1/2 orders the two branches at z = 0;
+    the tail at the clamp a = 9 is the global minimum."""
+    L = _lemma_lib()
+    out = (ctypes.c_double * 4)()
+    hi = struct.unpack("<I", struct.pack("<f", 9.0))[0]
+    L.lemma_scan(ctypes.c_uint32(0), ctypes.c_uint32(hi), ctypes.c_int(kind), out)
+    E, max_tail, _, min_tail = out[0], out[1], out[2], out[3]
+    h, gap = _hazard_min(kind)
+    h -= 2.0 * gap          # the hazard's slope is below 2 on [0, 9]
+    d = 2.0 ** -11
+    assert np.exp(-h * d) * (1 + E) / (1 - E) < 1.0, (h, E)
+    assert max_tail <= 0.5
+    assert min_tail == float(orc.phi(np.float32([-9.0]), kind)[0])
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_table_invariants_random_and_adversarial(orc, kind):
+    rng = np.random.default_rng(21 + kind)
+    for K, lo, hi, P in [(3, -128, 127, 16), (5, -511, 511, 16), (2, -3, 4, 5), (8, -20, 20, 12)]:
+        w, mu, sig = synth.random_params(rng, 1500, K)
+        wa, mua, siga = synth.adversarial_params(rng, 1500, K)
+        w, mu, sig = (np.ascontiguousarray(np.concatenate(x, axis=1))
+                      for x in ((w, wa), (mu, mua), (sig, siga)))
+        cfg = orc.make_cfg(K, lo, hi, P, 1, kind)
+        c = orc.cdf_table(cfg, w, mu, sig).astype(np.int64)
+        assert np.all(c[:, 0] == 0) and np.all(c[:, -1] == (1 << P))
+        f = np.diff(c, axis=1)
+        assert f.min() >= 1                      # every symbol stays codable
+        assert np.all(f.sum(axis=1) == (1 << P))  # frequencies sum to 2^P
+
+
+def test_k1_reduces_to_single_gaussian_bins(orc):
+    """K = 1: the column equals the quantized single-Gaussian bin model
+    Phi((y+1/2-mu)/sigma) - Phi((y-1/2-mu)/sigma), evaluated in binary64,
+    within one count (the floor may land on either side of an integer)."""
+    rng = np.random.default_rng(31)
+    n, lo, hi, P = 4000, -100, 100, 16
+    w, mu, sig = synth.random_params(rng, n, 1)
+    w[:] = 1.0
+    cfg = orc.make_cfg(1, lo, hi, P, 1)
+    c = orc.cdf_table(cfg, w, mu, sig).astype(np.int64)
+    N, M = hi - lo + 1, 1 << P
+    j = np.arange(1, N)
+    b = (lo + j - 0.5)[None, :]
+    s = np.clip(sig[0].astype(np.float64), 2.0 ** -10, 2.0 ** 10)[:, None]
+    F = ndtr((b - mu[0].astype(np.float64)[:, None]) / s)
+    ref = j[None, :] + np.floor(F * (M - N))
+    assert np.abs(c[:, 1:-1] - ref).max() <= 1
+
+
+def test_golden_textbook_columns(orc):
+    for case in read_golden("cdf_textbook.txt"):
+        K, lo, hi, P = case["K"][0], case["lo"][0], case["hi"][0], case["P"][0]
+        w = np.array(case["w"], np.float32).reshape(K, 1)
+        mu = np.array(case["mu"], np.float32).reshape(K, 1)
+        sig = np.array(case["sigma"], np.float32).reshape(K, 1)
+        for kind in (0,):
+            c = orc.cdf_table(orc.make_cfg(K, lo, hi, P, 1, kind), w, mu, sig)[0]
+            assert list(c) == case["c"], (case["name"], list(c))
+
+
+def test_inverse_equals_brute_force(orc):
+    """Linear scan = "the unique j with c_j <= slot < c_{j+1}" for every slot
+    of small alphabets (exhaustive over slots)."""
+    rng = np.random.default_rng(41)
+    for K, lo, hi, P in [(1, -1, 1, 4), (2, -2, 2, 5), (3, 0, 4, 6), (3, -3, 3, 8)]:
+        n = 40
+        w, mu, sig = synth.random_params(rng, n, K, sigma_max=3.0)
+        cfg = orc.make_cfg(K, lo, hi, P, 1)
+        c = orc.cdf_table(cfg, w, mu, sig).astype(np.int64)
+        M = 1 << P
+        slots = np.tile(np.arange(M, dtype=np.uint32), n)
+        ww, mm, ss = (np.ascontiguousarray(np.repeat(x, M, axis=1)) for x in (w, mu, sig))
+        j = orc.inverse(cfg, ww, mm, ss, slots).reshape(n, M)
+        for i in range(n):
+            for slot in range(M):
+                cand = [jj for jj in range(hi - lo + 1) if c[i, jj] <= slot < c[i, jj + 1]]
+                assert cand == [j[i, slot]]
