@@ -1,0 +1,208 @@
+"""ctypes binding of libflashgmm.so (argument marshalling only).
+
+Torch tensors supply device memory and the current HIP stream; every step of
+the coder runs in the library's HIP kernels. The binding raises if the
+library is missing or a tensor is not a contiguous device tensor of the
+expected dtype: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libflashgmm.so")
+
+OK, EINVAL, ERANGE, ECORRUPT, ENOSPC, EDEVICE, ENOMEM = range(7)
+
+
+class GmmError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_str(status)} (status {status})")
+
+
+class Cfg(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int32), ("lo", ctypes.c_int32), ("hi", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("num_streams", ctypes.c_int32),
+                ("cdf_kind", ctypes.c_int32)]
+
+
+class DecodeStats(ctypes.Structure):
+    _fields_ = [("hits", ctypes.c_uint64), ("misses", ctypes.c_uint64),
+                ("wave_all_hit", ctypes.c_uint64), ("wave_steps", ctypes.c_uint64)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+_CFG = ctypes.POINTER(Cfg)
+
+_SIGS = {
+    "gmm_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "gmm_version": (_I32, []),
+    "gmm_encode_max_words": (_I64, [_I64, _I32]),
+    "gmm_workspace_bytes": (_I64, [_CFG, _I64, _I32]),
+    "gmm_cdf_table": (ctypes.c_int, [_CFG, _I64, _P, _P, _P, _P, _P]),
+    "gmm_inverse_cdf": (ctypes.c_int, [_CFG, _I64, _P, _P, _P, _P, _P, _P]),
+    "gmm_encode": (ctypes.c_int, [_CFG, _I64, _P, _P, _P, _P, _P, _I64, _P, _P, _I64, _P, _P]),
+    "gmm_decode": (ctypes.c_int, [_CFG, _I64, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _I64,
+                                  _P, _P]),
+    "gmm_fast_recip_mismatches": (ctypes.c_int, [_P, _P]),
+}
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            if hasattr(L, name):
+                f = getattr(L, name)
+                f.restype, f.argtypes = res, args
+        _lib = L
+    return _lib
+
+
+def status_str(s: int) -> str:
+    return lib().gmm_status_str(int(s)).decode()
+
+
+def make_cfg(K, lo, hi, precision=16, streams=256, cdf_kind=0) -> Cfg:
+    return Cfg(int(K), int(lo), int(hi), int(precision), int(streams), int(cdf_kind))
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype, name: str):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _opt(t, dtype, name):
+    return _dev(t, dtype, name) if t is not None else ctypes.c_void_p(0)
+
+
+def _params(weights, means, scales, K):
+    for t, nm in ((weights, "weights"), (means, "means"), (scales, "scales")):
+        if t.dim() != 2 or t.shape[0] != K:
+            raise ValueError(f"{nm} must be a [K][n] plane tensor")
+    return (_dev(weights, torch.float32, "weights"), _dev(means, torch.float32, "means"),
+            _dev(scales, torch.float32, "scales"))
+
+
+def _check(st: int, what: str):
+    if st != OK:
+        raise GmmError(st, what)
+
+
+def max_words(n: int, streams: int) -> int:
+    return int(lib().gmm_encode_max_words(n, streams))
+
+
+def workspace_bytes(cfg: Cfg, n: int, op: int) -> int:
+    b = int(lib().gmm_workspace_bytes(ctypes.byref(cfg), n, op))
+    if b < 0:
+        raise GmmError(EINVAL, "workspace_bytes")
+    return b
+
+
+def cdf_table(cfg: Cfg, weights, means, scales) -> torch.Tensor:
+    n = weights.shape[1]
+    N = cfg.hi - cfg.lo + 1
+    out = torch.empty((n, N + 1), dtype=torch.int32, device=weights.device)
+    w, m, s = _params(weights, means, scales, cfg.K)
+    _check(lib().gmm_cdf_table(ctypes.byref(cfg), n, w, m, s, ctypes.c_void_p(out.data_ptr()),
+                               _stream()), "cdf_table")
+    return out
+
+
+def inverse_cdf(cfg: Cfg, weights, means, scales, slot: torch.Tensor) -> torch.Tensor:
+    n = weights.shape[1]
+    out = torch.empty((n,), dtype=torch.int32, device=weights.device)
+    w, m, s = _params(weights, means, scales, cfg.K)
+    _check(lib().gmm_inverse_cdf(ctypes.byref(cfg), n, w, m, s, _dev(slot, torch.int32, "slot"),
+                                 ctypes.c_void_p(out.data_ptr()), _stream()), "inverse_cdf")
+    return out
+
+
+def encode_into(cfg: Cfg, symbols, weights, means, scales, bitstream, offsets, ws=None,
+                status=None, stream=None) -> int:
+    """Low-level encode into caller buffers. With ``status`` (int32 device
+    tensor) the call is asynchronous; otherwise it returns the status."""
+    n = symbols.numel()
+    w, m, s = _params(weights, means, scales, cfg.K)
+    if offsets.numel() != cfg.num_streams + 1:
+        raise ValueError("offsets must hold num_streams + 1 entries")
+    return lib().gmm_encode(ctypes.byref(cfg), n, _dev(symbols, torch.int32, "symbols"), w, m, s,
+                            _dev(bitstream, torch.int16, "bitstream"), bitstream.numel(),
+                            _dev(offsets, torch.int64, "offsets"), _opt(ws, torch.uint8, "ws"),
+                            ws.numel() if ws is not None else 0,
+                            _opt(status, torch.int32, "status"), _stream(stream))
+
+
+def decode_into(cfg: Cfg, bitstream, offsets, weights, means, scales, symbols, total_words=None,
+                bracket=None, stats=None, ws=None, status=None, stream=None) -> int:
+    n = symbols.numel()
+    w, m, s = _params(weights, means, scales, cfg.K)
+    if offsets.numel() != cfg.num_streams + 1:
+        raise ValueError("offsets must hold num_streams + 1 entries")
+    tw = bitstream.numel() if total_words is None else int(total_words)
+    if tw > bitstream.numel():
+        raise ValueError("total_words exceeds the bitstream tensor")
+    bh = ctypes.c_void_p(bracket.handle) if bracket is not None else ctypes.c_void_p(0)
+    return lib().gmm_decode(ctypes.byref(cfg), n, _dev(bitstream, torch.int16, "bitstream"), tw,
+                            _dev(offsets, torch.int64, "offsets"), w, m, s,
+                            _dev(symbols, torch.int32, "symbols"), bh,
+                            _opt(stats, torch.int64, "stats"), _opt(ws, torch.uint8, "ws"),
+                            ws.numel() if ws is not None else 0,
+                            _opt(status, torch.int32, "status"), _stream(stream))
+
+
+def encode(symbols, weights, means, scales, lo, hi, precision=16, streams=256, cdf_kind=0):
+    """Encode int32 symbols [n] with [K][n] float32 parameter planes.
+    Returns (bitstream int16 tensor of the exact encoded size, offsets int64
+    tensor [streams+1]); bitstream words are uint16 values stored as int16."""
+    K = weights.shape[0]
+    cfg = make_cfg(K, lo, hi, precision, streams, cdf_kind)
+    n = symbols.numel()
+    cap = max_words(n, streams)
+    bs = torch.empty((max(cap, 1),), dtype=torch.int16, device=symbols.device)
+    off = torch.empty((streams + 1,), dtype=torch.int64, device=symbols.device)
+    _check(encode_into(cfg, symbols, weights, means, scales, bs, off), "encode")
+    total = int(off[-1].item())
+    return bs[:total], off
+
+
+def decode(bitstream, offsets, weights, means, scales, lo, hi, precision=16, streams=256,
+           cdf_kind=0, bracket=None, stats=None):
+    K = weights.shape[0]
+    cfg = make_cfg(K, lo, hi, precision, streams, cdf_kind)
+    n = weights.shape[1]
+    sym = torch.empty((n,), dtype=torch.int32, device=weights.device)
+    bs = bitstream if bitstream.numel() else torch.zeros(1, dtype=torch.int16,
+                                                         device=weights.device)
+    _check(decode_into(cfg, bs, offsets, weights, means, scales, sym,
+                       total_words=bitstream.numel(), bracket=bracket, stats=stats), "decode")
+    return sym
+
+
+def fast_recip_mismatches() -> int:
+    c = ctypes.c_uint64(0)
+    _check(lib().gmm_fast_recip_mismatches(ctypes.byref(c), _stream()), "fast_recip_check")
+    return int(c.value)

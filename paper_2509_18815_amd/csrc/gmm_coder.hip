@@ -1,0 +1,622 @@
+// GMM rANS coder kernels for gfx950 and the C ABI of libflashgmm.so
+// (declarations and argument contracts: include/flashgmm.h).
+//
+// Encode (FlashGMM Sec. III-A: the CDF is evaluated only at the coded
+// symbol's two boundaries) runs as
+//   k_enc_cdf   one thread per element: c_j and f_j of its symbol, packed
+//               into one uint32 (fully parallel over all n elements);
+//   k_enc_rans  one lane per stream: the integer rANS recurrence of Eq. (3)
+//               in reverse element order, renormalisation words written to
+//               the stream's scratch region in decoder order, then a
+//               wavefront/block prefix sum of the segment lengths;
+//   k_scan_blk  prefix sum of the per-block segment totals;
+//   k_pack      stream offsets and the compacted bitstream.
+// Decode (Sec. III-A: binary search over the monotone CDF) runs one lane per
+// stream with a branch-uniform search: every lane executes exactly
+// ceil(log2 N) CDF evaluations per symbol, with no early exit.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <string.h>
+
+#include <mutex>
+
+#include "../../include/flashgmm.h"
+#include "gmm_device.h"
+#include "gmm_host.h"
+
+using namespace fgmm;
+
+// ------------------------------------------------------------------ kernels
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+
+// Folds status bits into the call's status code.
+__global__ void k_finalize(const uint32_t* bits, int32_t* dev_status) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const uint32_t b = *bits;
+    int32_t code = GMM_OK;
+    if (b & kStInval) code = GMM_EINVAL;
+    else if (b & kStRange) code = GMM_ERANGE;
+    else if (b & kStNoSpace) code = GMM_ENOSPC;
+    else if (b & kStCorrupt) code = GMM_ECORRUPT;
+    *dev_status = code;
+  }
+}
+
+// Exhaustive check of recip_1_4 against IEEE division on every float in
+// [lo_bits, lo_bits + count).
+__global__ void k_recip_check(uint32_t lo_bits, uint32_t count, unsigned long long* mismatches) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  const float u = __uint_as_float(lo_bits + t);
+  const float a = recip_1_4(u);
+  const float b = 1.0f / u;
+  if (__float_as_uint(a) != __float_as_uint(b)) atomicAdd(mismatches, 1ull);
+}
+
+template <int K, int kKind, bool kFast>
+__global__ void k_cdf_table(QCfg q, int64_t n, const float* __restrict__ w,
+                            const float* __restrict__ mu, const float* __restrict__ sg,
+                            uint32_t* __restrict__ table) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t cols = (int64_t)q.N + 1;
+  if (t >= n * cols) return;
+  const int64_t i = t / cols;
+  const int32_t j = (int32_t)(t - i * cols);
+  float rw[K], rm[K], rs[K];
+  load_raw<K>(w, mu, sg, n, i, rw, rm, rs);
+  const Elem<K> e = make_elem<K>(rw, rm, rs);
+  table[t] = cdf_at<K, kKind, kFast>(e, q, j);
+}
+
+// Branch-uniform binary search for the j with c_j <= slot < c_{j+1}:
+// exactly `rounds` = ceil(log2 N) evaluations; on return c_lo = c_j and
+// c_hi = c_{j+1}. Once the interval has one symbol, mid = lo re-evaluates
+// c_lo and changes nothing, so every lane runs the same instruction stream.
+template <int K, int kKind, bool kFast>
+__device__ __forceinline__ int32_t search_bs(const Elem<K>& e, const QCfg& q, int rounds,
+                                             uint32_t slot, uint32_t& c_lo, uint32_t& c_hi) {
+  int32_t lo = 0, hi = q.N;
+  c_lo = 0;
+  c_hi = q.M;
+  for (int r = 0; r < rounds; ++r) {
+    const int32_t mid = (lo + hi) >> 1;
+    const uint32_t c = cdf_at<K, kKind, kFast>(e, q, mid);
+    const bool right = slot >= c;
+    lo = right ? mid : lo;
+    c_lo = right ? c : c_lo;
+    hi = right ? hi : mid;
+    c_hi = right ? c_hi : c;
+  }
+  return lo;
+}
+
+template <int K, int kKind, bool kFast>
+__global__ void k_inverse(QCfg q, int rounds, int64_t n, const float* __restrict__ w,
+                          const float* __restrict__ mu, const float* __restrict__ sg,
+                          const uint32_t* __restrict__ slot, int32_t* __restrict__ jout,
+                          uint32_t* status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float rw[K], rm[K], rs[K];
+  load_raw<K>(w, mu, sg, n, i, rw, rm, rs);
+  const Elem<K> e = make_elem<K>(rw, rm, rs);
+  uint32_t s = slot[i];
+  if (s >= q.M) {
+    atomicOr(status, kStInval);
+    s = q.M - 1;
+  }
+  uint32_t cl, ch;
+  jout[i] = search_bs<K, kKind, kFast>(e, q, rounds, s, cl, ch);
+}
+
+// Encode phase 1: (c_j << 16) | f_j per element (both fit 16 bits: c_j <
+// M <= 2^16 for j < N and f_j <= M - N + 1 < 2^16).
+template <int K, int kKind, bool kFast>
+__global__ void k_enc_cdf(QCfg q, int64_t n, const int32_t* __restrict__ sym,
+                          const float* __restrict__ w, const float* __restrict__ mu,
+                          const float* __restrict__ sg, uint32_t* __restrict__ cf,
+                          uint32_t* status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float rw[K], rm[K], rs[K];
+  load_raw<K>(w, mu, sg, n, i, rw, rm, rs);
+  int32_t j = sym[i] - q.lo;
+  if (j < 0 || j >= q.N) {
+    atomicOr(status, kStRange);
+    j = 0;
+  }
+  const Elem<K> e = make_elem<K>(rw, rm, rs);
+  const uint32_t c0 = cdf_at<K, kKind, kFast>(e, q, j);
+  const uint32_t c1 = cdf_at<K, kKind, kFast>(e, q, j + 1);
+  cf[i] = (c0 << 16) | (c1 - c0);
+}
+
+constexpr int kRansBlock = 256;
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t t = __shfl_up(v, d, 64);
+    if (lane >= d) v += t;
+  }
+  return v;
+}
+
+// Encode phase 2: one lane per stream. Stream s owns scratch words
+// [s*cap, (s+1)*cap); the k-th emitted word goes to s*cap + cap-1-k, so the
+// region's tail holds the words in the order the decoder reads them.
+// Then a block-wide exclusive scan of the segment lengths 2 + count.
+__global__ void __launch_bounds__(kRansBlock)
+    k_enc_rans(int64_t n, int64_t S, int P, const uint32_t* __restrict__ cf,
+               uint16_t* __restrict__ scratch, int64_t cap, uint32_t* __restrict__ xfin,
+               uint32_t* __restrict__ count, uint32_t* __restrict__ local_off,
+               int64_t* __restrict__ blk_total) {
+  __shared__ uint32_t wave_sum[kRansBlock / 64];
+  const int64_t s = (int64_t)blockIdx.x * kRansBlock + threadIdx.x;
+  uint32_t cnt = 0;
+  if (s < S) {
+    const int64_t ns = (s < n) ? (n - 1 - s) / S + 1 : 0;
+    uint32_t x = 1u << 16;
+    uint16_t* region = scratch + s * cap + (cap - 1);
+    const int shift = 32 - P;
+    int64_t p = ns - 1;
+    uint32_t nxt = (p >= 0) ? cf[s + p * S] : 0u;
+    for (; p >= 0; --p) {
+      const uint32_t v = nxt;
+      if (p > 0) nxt = cf[s + (p - 1) * S];
+      const uint32_t c = v >> 16;
+      const uint32_t f = v & 0xFFFFu;
+      if (x >= (f << shift)) {
+        region[-(int64_t)cnt] = (uint16_t)(x & 0xFFFFu);
+        ++cnt;
+        x >>= 16;
+      }
+      const uint32_t qd = x / f;
+      x = (qd << P) + (x - qd * f) + c;
+    }
+    xfin[s] = x;
+    count[s] = cnt;
+  }
+  // block exclusive scan of the segment lengths
+  const uint32_t len = (s < S) ? cnt + 2u : 0u;
+  const uint32_t incl = wave_incl_scan(len);
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 63) wave_sum[wv] = incl;
+  __syncthreads();
+  uint32_t base = 0;
+#pragma unroll
+  for (int k = 0; k < kRansBlock / 64; ++k) base += (k < wv) ? wave_sum[k] : 0u;
+  if (s < S) local_off[s] = base + incl - len;
+  if (threadIdx.x == kRansBlock - 1) {
+    uint32_t tot = 0;
+#pragma unroll
+    for (int k = 0; k < kRansBlock / 64; ++k) tot += wave_sum[k];
+    blk_total[blockIdx.x] = tot;
+  }
+}
+
+// Exclusive scan of nblk int64 block totals in one workgroup of 1024
+// threads, tile by tile with a running carry.
+constexpr int kScanBlock = 1024;
+__global__ void __launch_bounds__(kScanBlock)
+    k_scan_blk(int64_t nblk, const int64_t* __restrict__ tot, int64_t* __restrict__ pre) {
+  __shared__ int64_t wsum[kScanBlock / 64];
+  __shared__ int64_t carry_sh;
+  if (threadIdx.x == 0) carry_sh = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int64_t base = 0; base < nblk; base += kScanBlock) {
+    const int64_t i = base + threadIdx.x;
+    const int64_t v = (i < nblk) ? tot[i] : 0;
+    int64_t incl = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int64_t t = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += t;
+    }
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    int64_t off = carry_sh;
+    for (int k = 0; k < wv; ++k) off += wsum[k];
+    if (i < nblk) pre[i] = off + incl - v;
+    __syncthreads();
+    if (threadIdx.x == kScanBlock - 1) carry_sh = off + incl;
+    __syncthreads();
+  }
+}
+
+// Offsets and compaction: 16 lanes per stream copy its segment
+// [x lo, x hi, words...] to bitstream[offsets[s] ...].
+constexpr int kPackBlock = 256, kPackLanes = 16;
+__global__ void __launch_bounds__(kPackBlock)
+    k_pack(int64_t S, int64_t nblk, int64_t cap, const uint16_t* __restrict__ scratch,
+           const uint32_t* __restrict__ xfin, const uint32_t* __restrict__ count,
+           const uint32_t* __restrict__ local_off, const int64_t* __restrict__ blk_pre,
+           const int64_t* __restrict__ blk_total, int64_t* __restrict__ offsets,
+           uint16_t* __restrict__ bitstream, int64_t capacity, uint32_t* status) {
+  const int64_t s = (int64_t)blockIdx.x * (kPackBlock / kPackLanes) + threadIdx.x / kPackLanes;
+  const int l = threadIdx.x % kPackLanes;
+  const int64_t total = blk_pre[nblk - 1] + blk_total[nblk - 1];
+  const bool fits = total <= capacity;
+  if (!fits && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(status, kStNoSpace);
+  if (s >= S) return;
+  const int64_t off = blk_pre[s / kRansBlock] + (int64_t)local_off[s];
+  const uint32_t cnt = count[s];
+  if (l == 0) {
+    offsets[s] = off;
+    if (s == S - 1) offsets[S] = total;
+  }
+  if (!fits) return;
+  const uint32_t x = xfin[s];
+  const uint16_t* src = scratch + s * cap + (cap - (int64_t)cnt);
+  for (int64_t t = l; t < (int64_t)cnt + 2; t += kPackLanes) {
+    uint16_t wv;
+    if (t == 0) wv = (uint16_t)(x & 0xFFFFu);
+    else if (t == 1) wv = (uint16_t)(x >> 16);
+    else wv = src[t - 2];
+    bitstream[off + t] = wv;
+  }
+}
+
+// Decode: one lane per stream; the next element's parameters are loaded
+// while the current symbol is searched.
+template <int K, int kKind, bool kFast>
+__global__ void __launch_bounds__(64)
+    k_decode(QCfg q, int P, int rounds, int64_t n, int64_t S, const uint16_t* __restrict__ bs,
+             int64_t total_words, const int64_t* __restrict__ offsets,
+             const float* __restrict__ w, const float* __restrict__ mu,
+             const float* __restrict__ sg, int32_t* __restrict__ sym, uint32_t* status) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  const int64_t ns = (s < n) ? (n - 1 - s) / S + 1 : 0;
+  const int64_t a = offsets[s], b = offsets[s + 1];
+  if (a < 0 || b < a + 2 || b > total_words) {
+    for (int64_t p = 0; p < ns; ++p) sym[s + p * S] = q.lo;
+    atomicOr(status, kStCorrupt);
+    return;
+  }
+  uint32_t x = (uint32_t)bs[a] | ((uint32_t)bs[a + 1] << 16);
+  int64_t ptr = a + 2;
+  bool bad = x < (1u << 16);
+  const uint32_t mask = q.M - 1;
+  float nw[K], nm[K], nsg[K];
+  if (ns > 0) load_raw<K>(w, mu, sg, n, s, nw, nm, nsg);
+  for (int64_t p = 0; p < ns; ++p) {
+    const int64_t i = s + p * S;
+    float cw[K], cm[K], cs[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      cw[k] = nw[k];
+      cm[k] = nm[k];
+      cs[k] = nsg[k];
+    }
+    if (p + 1 < ns) load_raw<K>(w, mu, sg, n, i + S, nw, nm, nsg);
+    const Elem<K> e = make_elem<K>(cw, cm, cs);
+    const uint32_t slot = x & mask;
+    uint32_t cl, ch;
+    const int32_t j = search_bs<K, kKind, kFast>(e, q, rounds, slot, cl, ch);
+    sym[i] = q.lo + j;
+    x = (ch - cl) * (x >> P) + slot - cl;
+    if (x < (1u << 16)) {
+      uint32_t word = 0;
+      if (ptr < b) word = bs[ptr++];
+      else bad = true;
+      x = (x << 16) | word;
+    }
+  }
+  if (x != (1u << 16) || ptr != b) bad = true;
+  if (bad) atomicOr(status, kStCorrupt);
+}
+
+// ------------------------------------------------------------- host side
+
+namespace {
+
+int64_t align256(int64_t b) { return (b + 255) & ~(int64_t)255; }
+
+struct EncLayout {
+  int64_t status, cf, scratch, xfin, count, local_off, blk_total, blk_pre, bytes;
+  int64_t cap, nblk;
+};
+
+EncLayout enc_layout(int64_t n, int64_t S) {
+  EncLayout L;
+  L.cap = (n > 0) ? (n + S - 1) / S : 1;
+  L.nblk = (S + kRansBlock - 1) / kRansBlock;
+  int64_t o = 0;
+  L.status = o; o += 256;
+  L.cf = o; o += align256(4 * n);
+  L.scratch = o; o += align256(2 * S * L.cap);
+  L.xfin = o; o += align256(4 * S);
+  L.count = o; o += align256(4 * S);
+  L.local_off = o; o += align256(4 * S);
+  L.blk_total = o; o += align256(8 * L.nblk);
+  L.blk_pre = o; o += align256(8 * L.nblk);
+  L.bytes = o;
+  return L;
+}
+
+}  // namespace
+
+namespace fgmm {
+
+int check_cfg(const gmm_cfg* c, int64_t n) {
+  if (!c || n < 0) return GMM_EINVAL;
+  if (c->K < 1 || c->K > kMaxK) return GMM_EINVAL;
+  if (c->precision < 2 || c->precision > 16) return GMM_EINVAL;
+  if (c->num_streams < 1) return GMM_EINVAL;
+  if (c->cdf_kind != 0 && c->cdf_kind != 1) return GMM_EINVAL;
+  if (c->lo < -(1 << 22) || c->hi > (1 << 22) || c->hi <= c->lo) return GMM_EINVAL;
+  const int64_t N = (int64_t)c->hi - c->lo + 1;
+  const int64_t M = (int64_t)1 << c->precision;
+  if (N < 2 || N > M / 2) return GMM_EINVAL;
+  return GMM_OK;
+}
+
+QCfg make_qcfg(const gmm_cfg* c) {
+  QCfg q;
+  q.lo = c->lo;
+  q.N = c->hi - c->lo + 1;
+  q.M = 1u << c->precision;
+  q.span = (float)(q.M - (uint32_t)q.N);
+  return q;
+}
+
+int search_rounds(int32_t N) {
+  int r = 0;
+  while ((1 << r) < N) ++r;
+  return r;
+}
+
+// Per-device flag: recip_1_4 matches IEEE division on [1, 4) (checked once
+// per device, exhaustively, before the first coder launch on it).
+static std::mutex g_init_mu;
+static int g_fast_ok[64];  // 0 unknown, 1 verified, -1 mismatch
+
+int fast_recip_mismatches(unsigned long long* count, hipStream_t st) {
+  unsigned long long* d = nullptr;
+  if (hipMallocAsync((void**)&d, sizeof(unsigned long long), st) != hipSuccess) return GMM_ENOMEM;
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t*)d, 0u, (int64_t)2);
+  const uint32_t lo = 0x3f800000u;        // 1.0f
+  const uint32_t cnt = 0x40800000u - lo;  // every float in [1, 4)
+  hipLaunchKernelGGL(k_recip_check, dim3((cnt + 255) / 256), dim3(256), 0, st, lo, cnt, d);
+  unsigned long long h = 0;
+  hipError_t e1 = hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, st);
+  hipError_t e2 = hipStreamSynchronize(st);
+  (void)hipFreeAsync(d, st);
+  if (e1 != hipSuccess || e2 != hipSuccess) return GMM_EDEVICE;
+  *count = h;
+  return GMM_OK;
+}
+
+bool use_fast_recip(hipStream_t st) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return false;
+  std::lock_guard<std::mutex> lk(g_init_mu);
+  if (g_fast_ok[dev] == 0) {
+    unsigned long long mm = 1;
+    if (fast_recip_mismatches(&mm, st) != GMM_OK) return false;
+    g_fast_ok[dev] = (mm == 0) ? 1 : -1;
+  }
+  return g_fast_ok[dev] == 1;
+}
+
+int finish(uint32_t* bits, int32_t* dev_status, hipStream_t st) {
+  if (dev_status) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, bits, dev_status);
+    return hipGetLastError() == hipSuccess ? GMM_OK : GMM_EDEVICE;
+  }
+  uint32_t h = 0;
+  if (hipMemcpyAsync(&h, bits, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess)
+    return GMM_EDEVICE;
+  if (hipStreamSynchronize(st) != hipSuccess) return GMM_EDEVICE;
+  if (h & kStInval) return GMM_EINVAL;
+  if (h & kStRange) return GMM_ERANGE;
+  if (h & kStNoSpace) return GMM_ENOSPC;
+  if (h & kStCorrupt) return GMM_ECORRUPT;
+  return GMM_OK;
+}
+
+// Encode with an explicit workspace (used by the C entry point and plans).
+int encode_launch(const gmm_cfg* cfg, int64_t n, const int32_t* symbols, const float* w,
+                  const float* mu, const float* sg, uint16_t* bitstream, int64_t capacity,
+                  int64_t* offsets, char* ws, bool fast, hipStream_t st) {
+  const int64_t S = cfg->num_streams;
+  const EncLayout L = enc_layout(n, S);
+  const QCfg q = make_qcfg(cfg);
+  uint32_t* status = (uint32_t*)(ws + L.status);
+  uint32_t* cf = (uint32_t*)(ws + L.cf);
+  uint16_t* scratch = (uint16_t*)(ws + L.scratch);
+  uint32_t* xfin = (uint32_t*)(ws + L.xfin);
+  uint32_t* count = (uint32_t*)(ws + L.count);
+  uint32_t* local_off = (uint32_t*)(ws + L.local_off);
+  int64_t* blk_total = (int64_t*)(ws + L.blk_total);
+  int64_t* blk_pre = (int64_t*)(ws + L.blk_pre);
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, status, 0u, (int64_t)1);
+  if (n > 0) {
+    dispatch(cfg->K, cfg->cdf_kind, fast, [&](auto Kc, auto kc, auto fc) {
+      hipLaunchKernelGGL((k_enc_cdf<decltype(Kc)::value, decltype(kc)::value,
+                                    decltype(fc)::value>),
+                         dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, q, n, symbols, w,
+                         mu, sg, cf, status);
+    });
+  }
+  hipLaunchKernelGGL(k_enc_rans, dim3((unsigned)L.nblk), dim3(kRansBlock), 0, st, n, S,
+                     cfg->precision, cf, scratch, L.cap, xfin, count, local_off, blk_total);
+  hipLaunchKernelGGL(k_scan_blk, dim3(1), dim3(kScanBlock), 0, st, L.nblk, blk_total, blk_pre);
+  const int64_t per = kPackBlock / kPackLanes;
+  hipLaunchKernelGGL(k_pack, dim3((unsigned)((S + per - 1) / per)), dim3(kPackBlock), 0, st, S,
+                     L.nblk, L.cap, scratch, xfin, count, local_off, blk_pre, blk_total, offsets,
+                     bitstream, capacity, status);
+  return hipGetLastError() == hipSuccess ? GMM_OK : GMM_EDEVICE;
+}
+
+int decode_launch(const gmm_cfg* cfg, int64_t n, const uint16_t* bs, int64_t total_words,
+                  const int64_t* offsets, const float* w, const float* mu, const float* sg,
+                  int32_t* symbols, uint32_t* status, bool fast, hipStream_t st) {
+  const int64_t S = cfg->num_streams;
+  const QCfg q = make_qcfg(cfg);
+  const int rounds = search_rounds(q.N);
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, status, 0u, (int64_t)1);
+  dispatch(cfg->K, cfg->cdf_kind, fast, [&](auto Kc, auto kc, auto fc) {
+    hipLaunchKernelGGL((k_decode<decltype(Kc)::value, decltype(kc)::value, decltype(fc)::value>),
+                       dim3((unsigned)((S + 63) / 64)), dim3(64), 0, st, q, cfg->precision,
+                       rounds, n, S, bs, total_words, offsets, w, mu, sg, symbols, status);
+  });
+  return hipGetLastError() == hipSuccess ? GMM_OK : GMM_EDEVICE;
+}
+
+int64_t encode_ws_bytes(int64_t n, int64_t S) { return enc_layout(n, S).bytes; }
+
+}  // namespace fgmm
+
+// -------------------------------------------------------------- C ABI
+
+extern "C" {
+
+const char* gmm_status_str(int s) {
+  switch (s) {
+    case GMM_OK: return "ok";
+    case GMM_EINVAL: return "invalid argument";
+    case GMM_ERANGE: return "symbol outside the support";
+    case GMM_ECORRUPT: return "corrupt bitstream";
+    case GMM_ENOSPC: return "bitstream capacity too small";
+    case GMM_EDEVICE: return "HIP runtime error";
+    case GMM_ENOMEM: return "out of device memory";
+    default: return "unknown status";
+  }
+}
+
+int32_t gmm_version(void) { return 10000; }
+
+int64_t gmm_encode_max_words(int64_t n, int32_t S) {
+  if (n < 0 || S < 1) return -1;
+  return n + 2 * (int64_t)S;
+}
+
+int64_t gmm_workspace_bytes(const gmm_cfg* cfg, int64_t n, int32_t op) {
+  if (fgmm::check_cfg(cfg, n) != GMM_OK) return -1;
+  if (op == 0) return fgmm::encode_ws_bytes(n, cfg->num_streams);
+  if (op == 1) return 256;
+  return -1;
+}
+
+int gmm_cdf_table(const gmm_cfg* cfg, int64_t n, const float* w, const float* mu,
+                  const float* sg, uint32_t* table, void* stream) {
+  int st0 = fgmm::check_cfg(cfg, n);
+  if (st0) return st0;
+  if (n > 0 && (!w || !mu || !sg || !table)) return GMM_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const bool fast = fgmm::use_fast_recip(st);
+  const fgmm::QCfg q = fgmm::make_qcfg(cfg);
+  const int64_t total = n * ((int64_t)q.N + 1);
+  if (total == 0) return GMM_OK;
+  fgmm::dispatch(cfg->K, cfg->cdf_kind, fast, [&](auto Kc, auto kc, auto fc) {
+    hipLaunchKernelGGL((k_cdf_table<decltype(Kc)::value, decltype(kc)::value,
+                                    decltype(fc)::value>),
+                       dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, q, n, w, mu, sg,
+                       table);
+  });
+  if (hipGetLastError() != hipSuccess) return GMM_EDEVICE;
+  return hipStreamSynchronize(st) == hipSuccess ? GMM_OK : GMM_EDEVICE;
+}
+
+int gmm_inverse_cdf(const gmm_cfg* cfg, int64_t n, const float* w, const float* mu,
+                    const float* sg, const uint32_t* slot, int32_t* jout, void* stream) {
+  int st0 = fgmm::check_cfg(cfg, n);
+  if (st0) return st0;
+  if (n > 0 && (!w || !mu || !sg || !slot || !jout)) return GMM_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const bool fast = fgmm::use_fast_recip(st);
+  const fgmm::QCfg q = fgmm::make_qcfg(cfg);
+  const int rounds = fgmm::search_rounds(q.N);
+  uint32_t* status = nullptr;
+  if (hipMallocAsync((void**)&status, 256, st) != hipSuccess) return GMM_ENOMEM;
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, status, 0u, (int64_t)1);
+  if (n > 0) {
+    fgmm::dispatch(cfg->K, cfg->cdf_kind, fast, [&](auto Kc, auto kc, auto fc) {
+      hipLaunchKernelGGL((k_inverse<decltype(Kc)::value, decltype(kc)::value,
+                                    decltype(fc)::value>),
+                         dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, q, rounds, n, w,
+                         mu, sg, slot, jout, status);
+    });
+  }
+  int r = fgmm::finish(status, nullptr, st);
+  (void)hipFreeAsync(status, st);
+  return r;
+}
+
+int gmm_encode(const gmm_cfg* cfg, int64_t n, const int32_t* symbols, const float* w,
+               const float* mu, const float* sg, uint16_t* bitstream, int64_t capacity_words,
+               int64_t* offsets, void* ws, int64_t ws_bytes, int32_t* dev_status,
+               void* stream) {
+  int st0 = fgmm::check_cfg(cfg, n);
+  if (st0) return st0;
+  if (!offsets || capacity_words < 0) return GMM_EINVAL;
+  if (n > 0 && (!symbols || !w || !mu || !sg)) return GMM_EINVAL;
+  if (capacity_words > 0 && !bitstream) return GMM_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t need = fgmm::encode_ws_bytes(n, cfg->num_streams);
+  char* wsp = (char*)ws;
+  bool own = false;
+  if (!wsp) {
+    if (hipMallocAsync((void**)&wsp, need, st) != hipSuccess) return GMM_ENOMEM;
+    own = true;
+  } else if (ws_bytes < need) {
+    return GMM_EINVAL;
+  }
+  const bool fast = fgmm::use_fast_recip(st);
+  int r = fgmm::encode_launch(cfg, n, symbols, w, mu, sg, bitstream, capacity_words, offsets,
+                              wsp, fast, st);
+  if (r == GMM_OK) r = fgmm::finish((uint32_t*)wsp, dev_status, st);
+  if (own) (void)hipFreeAsync(wsp, st);
+  return r;
+}
+
+int gmm_decode(const gmm_cfg* cfg, int64_t n, const uint16_t* bitstream, int64_t total_words,
+               const int64_t* offsets, const float* w, const float* mu, const float* sg,
+               int32_t* symbols, const gmm_bracket* bracket, gmm_decode_stats* stats, void* ws,
+               int64_t ws_bytes, int32_t* dev_status, void* stream) {
+  int st0 = fgmm::check_cfg(cfg, n);
+  if (st0) return st0;
+  if (!offsets || total_words < 0) return GMM_EINVAL;
+  if (n > 0 && (!symbols || !w || !mu || !sg)) return GMM_EINVAL;
+  if (total_words > 0 && !bitstream) return GMM_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  char* wsp = (char*)ws;
+  bool own = false;
+  if (!wsp) {
+    if (hipMallocAsync((void**)&wsp, 256, st) != hipSuccess) return GMM_ENOMEM;
+    own = true;
+  } else if (ws_bytes < 256) {
+    return GMM_EINVAL;
+  }
+  const bool fast = fgmm::use_fast_recip(st);
+  int r;
+  if (bracket) {
+    (void)stats;
+    r = GMM_EINVAL;  // learned bracket not available in this build
+  } else {
+    r = fgmm::decode_launch(cfg, n, bitstream, total_words, offsets, w, mu, sg, symbols,
+                            (uint32_t*)wsp, fast, st);
+  }
+  if (r == GMM_OK) r = fgmm::finish((uint32_t*)wsp, dev_status, st);
+  if (own) (void)hipFreeAsync(wsp, st);
+  return r;
+}
+
+int gmm_fast_recip_mismatches(uint64_t* count, void* stream) {
+  if (!count) return GMM_EINVAL;
+  unsigned long long c = 0;
+  int r = fgmm::fast_recip_mismatches(&c, (hipStream_t)stream);
+  *count = c;
+  return r;
+}
+
+}  // extern "C"

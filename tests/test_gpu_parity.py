@@ -1,0 +1,226 @@
+"""GPU parity: the HIP library against the CPU oracle, bit-exact.
+
+Quantized CDF tables, the inverse CDF, bitstreams, offsets and decoded
+symbols must be identical to the oracle's on the same seeded inputs; status
+codes must agree on invalid, out-of-range, undersized and corrupted inputs.
+Sizes span several workgroups and ragged tails; the 4K latent is checked on
+sampled streams (the oracle re-encodes each sampled stream on its own).
+"""
+import numpy as np
+import pytest
+
+from conftest import read_golden
+from paper_2509_18815_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2509_18815_amd import api as a
+    a.lib()
+    assert torch.cuda.is_available()
+    return a
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def u16(t):
+    return t.cpu().numpy().view(np.uint16)
+
+
+def gpu_roundtrip(api, cfg, sym, w, mu, sig):
+    S = cfg.num_streams
+    dsym, dw, dm, ds = dev(sym), dev(w), dev(mu), dev(sig)
+    bs, off = api.encode(dsym, dw, dm, ds, cfg.lo, cfg.hi, cfg.precision, S, cfg.cdf_kind)
+    dec = api.decode(bs, off, dw, dm, ds, cfg.lo, cfg.hi, cfg.precision, S, cfg.cdf_kind)
+    return u16(bs), off.cpu().numpy(), dec.cpu().numpy()
+
+
+def test_fast_reciprocal_is_correctly_rounded(api):
+    """The reciprocal used for t = 1/(1 + p a) equals IEEE division on every
+    float in [1, 4) (exhaustive, on the device)."""
+    assert api.fast_recip_mismatches() == 0
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("K,lo,hi,P", [(1, -8, 7, 8), (3, -128, 127, 16), (5, -511, 511, 16),
+                                       (8, -30, 33, 12), (2, 0, 1, 2), (3, -255, 255, 16)])
+def test_cdf_table_bit_exact(api, orc, K, lo, hi, P, kind):
+    rng = np.random.default_rng(7 * K + hi + kind)
+    w, mu, sig = synth.random_params(rng, 700, K)
+    wa, ma, sa = synth.adversarial_params(rng, 700, K)
+    w, mu, sig = (np.ascontiguousarray(np.concatenate(x, axis=1)) for x in ((w, wa), (mu, ma),
+                                                                          (sig, sa)))
+    ocfg = orc.make_cfg(K, lo, hi, P, 1, kind)
+    ref = orc.cdf_table(ocfg, w, mu, sig)
+    got = api.cdf_table(api.make_cfg(K, lo, hi, P, 1, kind), dev(w), dev(mu), dev(sig))
+    got = got.cpu().numpy().view(np.uint32)
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_inverse_cdf_bit_exact(api, orc, kind):
+    rng = np.random.default_rng(77 + kind)
+    for K, lo, hi, P in [(3, -255, 255, 16), (5, -511, 511, 16), (1, -3, 3, 5)]:
+        n = 5000
+        w, mu, sig = synth.random_params(rng, n, K)
+        slot = rng.integers(0, 1 << P, size=n).astype(np.uint32)
+        ref = orc.inverse(orc.make_cfg(K, lo, hi, P, 1, kind), w, mu, sig, slot)
+        got = api.inverse_cdf(api.make_cfg(K, lo, hi, P, 1, kind), dev(w), dev(mu), dev(sig),
+                              dev(slot.view(np.int32)))
+        assert np.array_equal(got.cpu().numpy(), ref)
+
+
+def test_golden_hand_derived_bitstreams_on_gpu(api):
+    w = np.ones((1, 10), np.float32)
+    mu = np.zeros((1, 10), np.float32)
+    sig = np.ones((1, 10), np.float32)
+    for case in read_golden("rans_hand.txt"):
+        cfg = api.make_cfg(1, -2, 2, 8, case["S"][0])
+        sym = np.array(case["symbols"], np.int32)
+        bs, off, dec = gpu_roundtrip(api, cfg, sym, w, mu, sig)
+        assert list(off) == case["offsets"], case["name"]
+        assert list(bs) == case["bitstream"], case["name"]
+        assert np.array_equal(dec, sym)
+
+
+CASES = [  # (n, S, K, lo, hi, P, kind)
+    (0, 1, 3, -128, 127, 16, 0),
+    (1, 1, 1, -4, 3, 8, 0),
+    (5, 12, 2, -2, 2, 8, 0),
+    (1000, 7, 3, -128, 127, 16, 0),
+    (4099, 256, 3, -128, 127, 16, 1),
+    (70001, 300, 5, -511, 511, 16, 0),
+    (20000, 257, 8, -64, 63, 14, 0),
+    (33333, 1000, 4, -255, 255, 16, 1),
+]
+
+
+@pytest.mark.parametrize("n,S,K,lo,hi,P,kind", CASES)
+def test_encode_decode_bit_exact(api, orc, n, S, K, lo, hi, P, kind):
+    rng = np.random.default_rng(n + S + K)
+    w, mu, sig = synth.random_params(rng, n, K)
+    # symbols drawn from the model's own support with a few at the edges
+    sym = np.clip(np.rint(rng.normal(0, 8, size=n)), lo, hi).astype(np.int32)
+    if n > 10:
+        sym[:3] = [lo, hi, 0 if lo <= 0 <= hi else lo]
+    ocfg = orc.make_cfg(K, lo, hi, P, S, kind)
+    st, obs, ooff = orc.encode(ocfg, sym, w, mu, sig)
+    assert st == orc.OK
+    bs, off, dec = gpu_roundtrip(api, api.make_cfg(K, lo, hi, P, S, kind), sym, w, mu, sig)
+    assert np.array_equal(off, ooff)
+    assert np.array_equal(bs, obs)
+    assert np.array_equal(dec, sym)
+
+
+@pytest.mark.parametrize("name", ["c1", "c2a"])
+def test_workload_bit_exact(api, orc, name):
+    cfgd = synth.CONFIGS[name]
+    lat = synth.make_latents(cfgd)[0]
+    ocfg = orc.make_cfg(cfgd.K, cfgd.lo, cfgd.hi, cfgd.precision, lat.streams)
+    st, obs, ooff = orc.encode(ocfg, lat.symbols, lat.weights, lat.means, lat.scales)
+    assert st == orc.OK
+    bs, off, dec = gpu_roundtrip(api, api.make_cfg(cfgd.K, cfgd.lo, cfgd.hi, cfgd.precision,
+                                                   lat.streams),
+                                 lat.symbols, lat.weights, lat.means, lat.scales)
+    assert np.array_equal(off, ooff)
+    assert np.array_equal(bs, obs)
+    assert np.array_equal(dec, lat.symbols)
+
+
+def test_4k_latent_sampled_streams(api, orc):
+    """320x135x240, 65,536 streams, in the bench's launch configuration:
+    full round trip on the GPU; 48 sampled streams re-encoded and decoded by
+    the oracle one by one must match their GPU segments word for word."""
+    cfgd = synth.CONFIGS["c2b"]
+    lat = synth.make_latents(cfgd, backend="torch", device="cuda")[0]
+    S = lat.streams
+    bs, off = api.encode(lat.symbols, lat.weights, lat.means, lat.scales, cfgd.lo, cfgd.hi,
+                         cfgd.precision, S)
+    dec = api.decode(bs, off, lat.weights, lat.means, lat.scales, cfgd.lo, cfgd.hi,
+                     cfgd.precision, S)
+    assert torch.equal(dec, lat.symbols)
+    bs_h, off_h = u16(bs), off.cpu().numpy()
+    sym_h = lat.symbols.cpu().numpy()
+    w_h, m_h, s_h = (x.cpu().numpy() for x in (lat.weights, lat.means, lat.scales))
+    rng = np.random.default_rng(3)
+    sample = np.concatenate([[0, 1, S - 1], rng.choice(S, 45, replace=False)])
+    ocfg1 = orc.make_cfg(cfgd.K, cfgd.lo, cfgd.hi, cfgd.precision, 1)
+    for s in sample:
+        idx = np.arange(s, lat.n, S)
+        sub = [np.ascontiguousarray(x[..., idx]) for x in (sym_h, w_h, m_h, s_h)]
+        st, obs, ooff = orc.encode(ocfg1, *sub)
+        assert st == orc.OK
+        seg = bs_h[off_h[s]:off_h[s + 1]]
+        assert np.array_equal(seg, obs), int(s)
+        st, odec = orc.decode(ocfg1, seg, np.array([0, seg.size], np.int64), *sub[1:])
+        assert st == orc.OK and np.array_equal(odec, sub[0])
+
+
+def test_error_codes_match_oracle(api, orc):
+    rng = np.random.default_rng(5)
+    n, K, S = 3000, 3, 37
+    w, mu, sig = synth.random_params(rng, n, K)
+    sym = rng.integers(-20, 21, size=n).astype(np.int32)
+    dw, dm, ds = dev(w), dev(mu), dev(sig)
+    cfg = api.make_cfg(K, -32, 31, 16, S)
+    ocfg = orc.make_cfg(K, -32, 31, 16, S)
+    # invalid configuration: rejected on the host
+    bad = api.make_cfg(K, -32, 31, 6, S)
+    bsb = torch.empty(n + 2 * S, dtype=torch.int16, device="cuda")
+    offb = torch.empty(S + 1, dtype=torch.int64, device="cuda")
+    assert api.encode_into(bad, dev(sym), dw, dm, ds, bsb, offb) == api.EINVAL
+    # out of range
+    s2 = sym.copy()
+    s2[1234] = 32
+    assert api.encode_into(cfg, dev(s2), dw, dm, ds, bsb, offb) == api.ERANGE
+    # capacity: offsets written, equal to the oracle's
+    st, obs, ooff = orc.encode(ocfg, sym, w, mu, sig)
+    small = torch.empty(int(ooff[-1]) - 1, dtype=torch.int16, device="cuda")
+    assert api.encode_into(cfg, dev(sym), dw, dm, ds, small, offb) == api.ENOSPC
+    assert np.array_equal(offb.cpu().numpy(), ooff)
+    # corrupted streams: same status and the same (deterministic) symbols
+    dec = torch.empty(n, dtype=torch.int32, device="cuda")
+    flipped = obs.copy()
+    flipped[ooff[3] + 2] ^= 0x0100
+    trunc_off = ooff.copy()
+    trunc_off[4:] -= 1
+    trunc = np.delete(obs, ooff[4] - 1)
+    badoff = ooff.copy()
+    badoff[5] = badoff[4] + 1
+    for bsx, offx in [(flipped, ooff), (trunc, trunc_off), (obs, badoff)]:
+        ost, osym = orc.decode(ocfg, bsx, offx, w, mu, sig)
+        assert ost == orc.ECORRUPT
+        gst = api.decode_into(cfg, dev(bsx.view(np.int16)), dev(offx), dw, dm, ds, dec)
+        assert gst == api.ECORRUPT
+        assert np.array_equal(dec.cpu().numpy(), osym)
+    assert api.decode_into(cfg, dev(obs.view(np.int16)), dev(ooff), dw, dm, ds, dec) == api.OK
+    assert np.array_equal(dec.cpu().numpy(), sym)
+
+
+def test_async_status_and_determinism(api):
+    rng = np.random.default_rng(9)
+    n, K, S = 100_000, 3, 512
+    w, mu, sig = synth.random_params(rng, n, K)
+    sym = np.clip(np.rint(rng.normal(0, 5, size=n)), -128, 127).astype(np.int32)
+    cfg = api.make_cfg(K, -128, 127, 16, S)
+    dsym, dw, dm, ds = dev(sym), dev(w), dev(mu), dev(sig)
+    outs = []
+    for rep in range(3):
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            bs = torch.empty(n + 2 * S, dtype=torch.int16, device="cuda")
+            off = torch.empty(S + 1, dtype=torch.int64, device="cuda")
+            ws = torch.empty(api.workspace_bytes(cfg, n, 0), dtype=torch.uint8, device="cuda")
+            status = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+            assert api.encode_into(cfg, dsym, dw, dm, ds, bs, off, ws=ws, status=status) == 0
+        stream.synchronize()
+        assert int(status.item()) == api.OK
+        outs.append((u16(bs)[: int(off[-1].item())].copy(), off.cpu().numpy()))
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
