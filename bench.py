@@ -102,12 +102,203 @@ def cpu_baseline(lat_host, cfgd):
             "bitstream_equal_to_gpu": bool(np.array_equal(bs, lat_host.get("gpu_bs", bs)))}
 
 
+def summarize_prof(root: str) -> str:
+    """Markdown summary of rocprofv3 CSV output under root/{trace,fetch,write,
+    valu}: per (kernel, grid) mean duration, HBM bytes from FETCH_SIZE and
+    WRITE_SIZE scaled so that the 1 GiB calibration copy reads 1 GiB each
+    way, and VALU instruction counts."""
+    import collections
+    import csv
+    import glob
+
+    def rows(sub, suffix):
+        out = []
+        for f in glob.glob(os.path.join(root, sub, f"*{suffix}")):
+            out += list(csv.DictReader(open(f)))
+        return out
+
+    def short(name):
+        name = name.replace("void ", "")
+        return name.split("(")[0] if "(" in name else name
+
+    dur = collections.defaultdict(list)
+    for r in rows("trace", "kernel_trace.csv"):
+        dur[(short(r["Kernel_Name"]), int(r.get("Grid_Size") or r["Grid_Size_X"]))].append(
+            (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    ctr = collections.defaultdict(list)
+    for sub in ("fetch", "write", "valu"):
+        for r in rows(sub, "counter_collection.csv"):
+            ctr[(short(r["Kernel_Name"]), int(r["Grid_Size"]), r["Counter_Name"])].append(
+                float(r["Counter_Value"]))
+    mean = lambda v: sum(v) / len(v) if v else float("nan")  # noqa: E731
+    # calibration: the largest copyBuffer dispatch is the 1 GiB copy
+    cal = [k for k in ctr if k[0].startswith("__amd_rocclr_copyBuffer") and k[2] == "WRITE_SIZE"]
+    gib_kib = float(1 << 20)
+    fetch_f = write_f = float("nan")
+    if cal:
+        kw = max(cal, key=lambda k: mean(ctr[k]))
+        write_f = gib_kib / mean(ctr[kw])
+        kf = (kw[0], kw[1], "FETCH_SIZE")
+        if kf in ctr:
+            fetch_f = gib_kib / mean(ctr[kf])
+    lines = ["| kernel | grid | calls | mean us | HBM read MB | HBM write MB | "
+             "VALU instr/wave | waves | GRBM_GUI_ACTIVE |", "|---|---|---|---|---|---|---|---|---|"]
+    keys = sorted({(k[0], k[1]) for k in dur} | {(k[0], k[1]) for k in ctr},
+                  key=lambda k: -mean(dur.get(k, [0])) * len(dur.get(k, [0])))
+    for k in keys:
+        if not (k[0].startswith("k_") or k[0].startswith("__amd_rocclr_copyBuffer")):
+            continue
+        d = dur.get(k, [])
+        fe = mean(ctr.get((k[0], k[1], "FETCH_SIZE"), [])) * fetch_f * 1024 / 1e6
+        wr = mean(ctr.get((k[0], k[1], "WRITE_SIZE"), [])) * write_f * 1024 / 1e6
+        vi = mean(ctr.get((k[0], k[1], "SQ_INSTS_VALU"), []))
+        wv = mean(ctr.get((k[0], k[1], "SQ_WAVES"), []))
+        gg = mean(ctr.get((k[0], k[1], "GRBM_GUI_ACTIVE"), []))
+        lines.append(f"| {k[0]} | {k[1]} | {len(d)} | {mean(d):.2f} | {fe:.2f} | {wr:.2f} | "
+                     f"{vi / wv if wv == wv and wv else float('nan'):.0f} | {wv:.0f} | {gg:.0f} |")
+    head = [f"FETCH_SIZE scale {fetch_f:.4f}, WRITE_SIZE scale {write_f:.4f} "
+            "(so that the 1 GiB calibration copy reads 1 GiB each way).", ""]
+    return "\n".join(head + lines)
+
+
+def kernel_source_hash() -> str:
+    """sha256 of the HIP sources: counter figures recorded for one version
+    of the kernels are reported only while the sources are unchanged."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2509_18815_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*"))):
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_record(root: str, kernel: str, grid: int) -> dict:
+    """HBM bytes per launch of one kernel dispatch shape from the counter
+    CSVs (FETCH_SIZE and WRITE_SIZE scaled by the 1 GiB copy)."""
+    import collections
+    import csv
+    import glob
+
+    ctr = collections.defaultdict(list)
+    for sub in ("fetch", "write"):
+        for f in glob.glob(os.path.join(root, sub, "*counter_collection.csv")):
+            for r in csv.DictReader(open(f)):
+                ctr[(r["Kernel_Name"].replace("void ", "").split("(")[0], int(r["Grid_Size"]),
+                     r["Counter_Name"])].append(float(r["Counter_Value"]))
+    mean = lambda v: sum(v) / len(v)  # noqa: E731
+    cal = max((k for k in ctr if k[0].startswith("__amd_rocclr_copyBuffer")
+               and k[2] == "WRITE_SIZE"), key=lambda k: mean(ctr[k]))
+    wf = float(1 << 20) / mean(ctr[cal])
+    ff = float(1 << 20) / mean(ctr[(cal[0], cal[1], "FETCH_SIZE")])
+    rd = mean(ctr[(kernel, grid, "FETCH_SIZE")]) * ff * 1024
+    wr = mean(ctr[(kernel, grid, "WRITE_SIZE")]) * wf * 1024
+    return {"kernel": kernel, "grid": grid, "read_bytes": rd, "write_bytes": wr,
+            "traffic_bytes": rd + wr, "fetch_scale": ff, "write_scale": wf,
+            "source_sha": kernel_source_hash()}
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_decode_4k_320x135x240_traffic.json")
+
+
+def time_events(fn, reps, stream):
+    import torch
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    fn()
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    b.synchronize()
+    return a.elapsed_time(b) / 1e3 / reps
+
+
+def batched_form(api, synth, name, dev, reps=5):
+    """One plan (hipGraph of persistent kernels, autotuned) per direction over
+    a batch of uneven latents, against a loop of single-latent calls on the
+    same buffers; round trip verified."""
+    import torch
+    cfgd = synth.CONFIGS[name]
+    lats = synth.make_latents(cfgd, backend="torch", device=dev)
+    ns, Ss = [L.n for L in lats], [L.streams for L in lats]
+    n_tot = sum(ns)
+    stream = torch.cuda.current_stream()
+    pe = api.Plan(cfgd.K, cfgd.lo, cfgd.hi, cfgd.precision, ns, Ss, op=0, autotune=True)
+    pd = api.Plan(cfgd.K, cfgd.lo, cfgd.hi, cfgd.precision, ns, Ss, op=1, autotune=True)
+    io, dio = [], []
+    for L in lats:
+        cap = L.n + 2 * L.streams
+        e = {"symbols": L.symbols, "weights": L.weights, "means": L.means, "scales": L.scales,
+             "bitstream": torch.empty(cap, dtype=torch.int16, device=dev), "words": cap,
+             "offsets": torch.empty(L.streams + 1, dtype=torch.int64, device=dev)}
+        io.append(e)
+    st_e = torch.zeros(len(lats), dtype=torch.int32, device=dev)
+    st_d = torch.zeros(len(lats), dtype=torch.int32, device=dev)
+    assert pe.run(io) == 0
+    for L, e in zip(lats, io):
+        dio.append({"weights": L.weights, "means": L.means, "scales": L.scales,
+                    "bitstream": e["bitstream"], "words": int(e["offsets"][-1].item()),
+                    "offsets": e["offsets"],
+                    "decoded": torch.empty(L.n, dtype=torch.int32, device=dev)})
+    assert pd.run(dio) == 0
+    t_enc = time_events(lambda: pe.run(io, status=st_e), reps, stream)
+    t_dec = time_events(lambda: pd.run(dio, status=st_d), reps, stream)
+    torch.cuda.synchronize()
+    assert st_e.abs().sum().item() == 0 and st_d.abs().sum().item() == 0
+    for L, d in zip(lats, dio):
+        assert torch.equal(d["decoded"], L.symbols), "batched round trip failed"
+    words = sum(int(e["offsets"][-1].item()) for e in io)
+    # single-latent calls on the same buffers, for comparison
+    ws = [torch.empty(api.workspace_bytes(api.make_cfg(cfgd.K, cfgd.lo, cfgd.hi, cfgd.precision,
+                                                       L.streams), L.n, 0),
+                      dtype=torch.uint8, device=dev) for L in lats]
+    st1 = torch.zeros(1, dtype=torch.int32, device=dev)
+
+    def loop_enc():
+        for L, e, w in zip(lats, io, ws):
+            api.encode_into(api.make_cfg(cfgd.K, cfgd.lo, cfgd.hi, cfgd.precision, L.streams),
+                            L.symbols, L.weights, L.means, L.scales, e["bitstream"],
+                            e["offsets"], ws=w, status=st1)
+
+    def loop_dec():
+        for L, d in zip(lats, dio):
+            api.decode_into(api.make_cfg(cfgd.K, cfgd.lo, cfgd.hi, cfgd.precision, L.streams),
+                            d["bitstream"], d["offsets"], L.weights, L.means, L.scales,
+                            d["decoded"], total_words=d["words"], status=st1)
+    t_enc1 = time_events(loop_enc, 2, stream)
+    t_dec1 = time_events(loop_dec, 2, stream)
+    out = {"latents": len(lats), "n": n_tot, "K": cfgd.K, "support": [cfgd.lo, cfgd.hi],
+           "encode_sym_s": n_tot / t_enc, "decode_sym_s": n_tot / t_dec,
+           "roundtrip_sym_s": n_tot / (t_enc + t_dec),
+           "bits_per_symbol": 16.0 * words / n_tot,
+           "encode_plan": pe.info(), "decode_plan": pd.info(),
+           "single_call_loop": {"encode_sym_s": n_tot / t_enc1, "decode_sym_s": n_tot / t_dec1}}
+    pe.close()
+    pd.close()
+    return out
+
+
 def main():
+    if len(sys.argv) > 2 and sys.argv[1] == "--summarize-prof":
+        print(summarize_prof(sys.argv[2]))
+        return
+    if len(sys.argv) > 2 and sys.argv[1] == "--record-traffic":
+        rec = traffic_record(sys.argv[2], "k_decode<3, 0, true>", 65536)
+        with open(TRAFFIC_FILE, "w") as fh:
+            json.dump(rec, fh, indent=1)
+        print(json.dumps(rec))
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="c3",
+                    help="comma list of extra forms to measure after the timed steps "
+                         "(c3: batch of 64 latents; none)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -177,9 +368,14 @@ def main():
     K, N = big.cfgd.K, big.cfgd.hi - big.cfgd.lo + 1
     dec_t = ev[("c2b", "decode")]
     achieved = decode_flops_per_symbol(K, N) * big.n / dec_t / 1e12
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        rec = json.load(open(TRAFFIC_FILE))
+        if rec.get("source_sha") == kernel_source_hash():
+            traffic = rec["traffic_bytes"]
     roofline = {"bound": "alu", "kernel": "k_decode (4K latent, 65,536 streams)",
                 "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
                 "flops_per_symbol": decode_flops_per_symbol(K, N),
                 "launch_ms": round(dec_t * 1e3, 4)}
     out = {
@@ -194,6 +390,15 @@ def main():
         "roofline": roofline,
         "forms": forms,
     }
+    for form in [f for f in args.forms.split(",") if f and f != "none"]:
+        forms[form + "_batched"] = batched_form(api, synth, form, dev)
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not args.no_cpu_baseline:
         L = lats["c2a"]
         import numpy as np

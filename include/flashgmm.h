@@ -132,6 +132,95 @@ int gmm_decode(const gmm_cfg* cfg, int64_t n, const uint16_t* bitstream, int64_t
                gmm_decode_stats* stats, void* ws, int64_t ws_bytes, int32_t* dev_status,
                void* stream);
 
+/* ---- Batched coding of many latents (plans) ----
+ * A plan fixes the common configuration (cfg with num_streams ignored) and
+ * the shapes of B latents: n_b[b] elements coded in S_b[b] streams. Its
+ * encode (op = 0) or decode (op = 1) of the whole batch runs as one hipGraph
+ * of persistent kernels that share the latents' streams across the chip
+ * (longest streams first from an atomic work queue). Each latent's
+ * bitstream, offsets and symbols are exactly those of gmm_encode /
+ * gmm_decode with cfg.num_streams = S_b[b]. Not part of the paper: a
+ * throughput form for serving many images at once. */
+typedef struct gmm_plan gmm_plan;
+
+/* Flag for gmm_plan_create: time every candidate launch shape (lanes per
+ * stream, schedule, waves per compute unit) on the real shapes at the first
+ * gmm_plan_exec and keep the fastest; with the environment variable
+ * FLASHGMM_TUNE_CACHE naming a file, results are cached there by shape
+ * signature. Without it a fixed default shape is used. */
+#define GMM_PLAN_AUTOTUNE 1
+
+/* Buffers of one latent for gmm_plan_exec (all [device]):
+ *  symbols   encode input, int32 [n]
+ *  weights, means, scales   parameter planes, float32 [K][n]
+ *  bitstream encode output / decode input, uint16
+ *  words     encode: capacity of bitstream in words; decode: its length
+ *  offsets   int64 [S+1]: encode output / decode input
+ *  decoded   decode output, int32 [n] */
+typedef struct gmm_latent_io {
+  const int32_t* symbols;
+  const float* weights;
+  const float* means;
+  const float* scales;
+  uint16_t* bitstream;
+  int64_t words;
+  int64_t* offsets;
+  int32_t* decoded;
+} gmm_latent_io;
+
+/* Chosen launch shape of a plan (after its first execution). schedule:
+ * 0 one work item per workgroup, 1 persistent with an atomic queue,
+ * 2 persistent with a static round-robin assignment. */
+typedef struct gmm_plan_info_t {
+  int32_t tuned, lanes_per_stream, schedule, waves_per_cu, candidates, graph_captured;
+  double best_ms;
+} gmm_plan_info_t;
+
+/* Creates a plan (allocates its device workspace and tables). *out [host]
+ * receives the handle; release it with gmm_plan_destroy. */
+int gmm_plan_create(const gmm_cfg* common, int32_t B, const int64_t* n_b, const int32_t* S_b,
+                    int32_t op, int32_t flags, gmm_plan** out);
+
+/* Runs the plan on io [host array of B]. dev_status [device, int32 [B],
+ * nullable]: if NULL the call synchronises and returns the first failing
+ * latent's status (or GMM_OK); otherwise it is asynchronous and the
+ * per-latent status codes are stored there. The first call tunes (with
+ * GMM_PLAN_AUTOTUNE) and captures the graph; a call with buffers different
+ * from the previous call's synchronises the stream before refreshing the
+ * plan's descriptor table. */
+int gmm_plan_exec(gmm_plan* plan, const gmm_latent_io* io, int32_t* dev_status, void* stream);
+
+/* Reports the plan's chosen launch shape. */
+int gmm_plan_info(const gmm_plan* plan, gmm_plan_info_t* info);
+
+/* Forces a launch shape (skipping the tuner) and drops the captured graph;
+ * the next gmm_plan_exec captures again. lanes 1, 2, 4, 8 or 16 (decode
+ * only; encode requires 1), schedule 0..2, waves_per_cu 1..64. For tests
+ * and sweeps: the output never depends on it. */
+int gmm_plan_set_config(gmm_plan* plan, int32_t lanes, int32_t schedule, int32_t waves_per_cu);
+
+/* The tuner's candidate launch shapes: writes up to max_count triples
+ * (lanes, schedule, waves_per_cu) to out [host, int32 3*max_count] and
+ * returns the number of candidates (-1 on a NULL plan). */
+int gmm_plan_candidates(const gmm_plan* plan, int32_t* out, int32_t max_count);
+
+/* Releases a plan (waits for its work to finish). */
+int gmm_plan_destroy(gmm_plan* plan);
+
+/* Launch shape of later gmm_decode calls in this process (all threads):
+ * lanes = 1 runs one wavefront lane per stream with a binary search
+ * (ceil(log2 N) CDF evaluations per symbol); lanes = 2, 4, 8, 16 or 32 lets
+ * that many lanes share a stream and search (lanes+1)-ary, cutting the
+ * sequential rounds to ceil(log_{lanes+1} N) at the cost of more total
+ * evaluations (for latents with few streams); 0 (default) chooses from the
+ * stream count. Output is identical for every choice. GMM_EINVAL otherwise. */
+int gmm_set_decode_lanes(int32_t lanes);
+
+/* Diagnostic: number of floats u in [2^-10, 2^10] on which the coder's fused
+ * reciprocal differs from IEEE division (*count [host]); the library uses
+ * the fused form on a device only when this is 0. Synchronous. */
+int gmm_fast_recip_mismatches(uint64_t* count, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -35,6 +35,20 @@ class DecodeStats(ctypes.Structure):
                 ("wave_all_hit", ctypes.c_uint64), ("wave_steps", ctypes.c_uint64)]
 
 
+class LatentIO(ctypes.Structure):
+    _fields_ = [("symbols", ctypes.c_void_p), ("weights", ctypes.c_void_p),
+                ("means", ctypes.c_void_p), ("scales", ctypes.c_void_p),
+                ("bitstream", ctypes.c_void_p), ("words", ctypes.c_int64),
+                ("offsets", ctypes.c_void_p), ("decoded", ctypes.c_void_p)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("tuned", ctypes.c_int32), ("lanes_per_stream", ctypes.c_int32),
+                ("schedule", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
+                ("candidates", ctypes.c_int32), ("graph_captured", ctypes.c_int32),
+                ("best_ms", ctypes.c_double)]
+
+
 _lib = None
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
@@ -52,6 +66,13 @@ _SIGS = {
     "gmm_decode": (ctypes.c_int, [_CFG, _I64, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _I64,
                                   _P, _P]),
     "gmm_fast_recip_mismatches": (ctypes.c_int, [_P, _P]),
+    "gmm_set_decode_lanes": (ctypes.c_int, [_I32]),
+    "gmm_plan_create": (ctypes.c_int, [_CFG, _I32, _P, _P, _I32, _I32, _P]),
+    "gmm_plan_exec": (ctypes.c_int, [_P, _P, _P, _P]),
+    "gmm_plan_info": (ctypes.c_int, [_P, _P]),
+    "gmm_plan_set_config": (ctypes.c_int, [_P, _I32, _I32, _I32]),
+    "gmm_plan_candidates": (ctypes.c_int, [_P, _P, _I32]),
+    "gmm_plan_destroy": (ctypes.c_int, [_P]),
 }
 
 
@@ -202,7 +223,97 @@ def decode(bitstream, offsets, weights, means, scales, lo, hi, precision=16, str
     return sym
 
 
+def set_decode_lanes(lanes: int) -> None:
+    """Lanes per stream of later decodes (0 = automatic); output unchanged."""
+    _check(lib().gmm_set_decode_lanes(int(lanes)), "set_decode_lanes")
+
+
 def fast_recip_mismatches() -> int:
     c = ctypes.c_uint64(0)
     _check(lib().gmm_fast_recip_mismatches(ctypes.byref(c), _stream()), "fast_recip_check")
     return int(c.value)
+
+
+PLAN_AUTOTUNE = 1
+SCHEDULES = ("flat", "dynamic", "static")
+
+
+class Plan:
+    """Batched encode (op=0) or decode (op=1) of B latents with fixed shapes
+    (n_b elements, S_b streams each), run as one captured hipGraph."""
+
+    def __init__(self, K, lo, hi, precision, ns, streams, op, autotune=True, cdf_kind=0):
+        self.cfg = make_cfg(K, lo, hi, precision, 1, cdf_kind)
+        self.ns = [int(v) for v in ns]
+        self.streams = [int(v) for v in streams]
+        self.B, self.op = len(self.ns), int(op)
+        n_arr = (ctypes.c_int64 * self.B)(*self.ns)
+        s_arr = (ctypes.c_int32 * self.B)(*self.streams)
+        h = ctypes.c_void_p(0)
+        _check(lib().gmm_plan_create(ctypes.byref(self.cfg), self.B, n_arr, s_arr, self.op,
+                                     PLAN_AUTOTUNE if autotune else 0, ctypes.byref(h)),
+               "plan_create")
+        self.handle = h
+        self._io = (LatentIO * self.B)()
+
+    def _fill(self, latents):
+        if len(latents) != self.B:
+            raise ValueError("one io dict per latent")
+        for b, d in enumerate(latents):
+            x = self._io[b]
+            K = self.cfg.K
+            if self.ns[b] != d["weights"].shape[1]:
+                raise ValueError(f"latent {b}: n differs from the plan")
+            w, m, s = _params(d["weights"], d["means"], d["scales"], K)
+            x.weights, x.means, x.scales = w.value, m.value, s.value
+            if d["offsets"].numel() != self.streams[b] + 1:
+                raise ValueError(f"latent {b}: offsets must hold S+1 entries")
+            x.offsets = _dev(d["offsets"], torch.int64, "offsets").value
+            bs = d["bitstream"]
+            x.bitstream = _dev(bs, torch.int16, "bitstream").value
+            x.words = int(d.get("words", bs.numel()))
+            if x.words > bs.numel():
+                raise ValueError("words exceeds the bitstream tensor")
+            if self.op == 0:
+                x.symbols = _dev(d["symbols"], torch.int32, "symbols").value
+                x.decoded = None
+            else:
+                x.decoded = _dev(d["decoded"], torch.int32, "decoded").value
+                x.symbols = None
+
+    def run(self, latents, status=None, stream=None) -> int:
+        """latents: list of dicts of tensors (weights, means, scales,
+        bitstream, offsets, words?, symbols | decoded). With ``status`` (int32
+        device tensor [B]) asynchronous; otherwise returns the worst status."""
+        self._fill(latents)
+        return lib().gmm_plan_exec(self.handle, self._io, _opt(status, torch.int32, "status"),
+                                   _stream(stream))
+
+    def info(self) -> dict:
+        inf = PlanInfo()
+        _check(lib().gmm_plan_info(self.handle, ctypes.byref(inf)), "plan_info")
+        return {"tuned": bool(inf.tuned), "lanes_per_stream": inf.lanes_per_stream,
+                "schedule": SCHEDULES[inf.schedule], "waves_per_cu": inf.waves_per_cu,
+                "candidates": inf.candidates, "graph_captured": bool(inf.graph_captured),
+                "best_ms": inf.best_ms}
+
+    def set_config(self, lanes, schedule, waves_per_cu):
+        _check(lib().gmm_plan_set_config(self.handle, lanes, schedule, waves_per_cu),
+               "plan_set_config")
+
+    def candidates(self):
+        n = lib().gmm_plan_candidates(self.handle, None, 0)
+        buf = (ctypes.c_int32 * (3 * max(n, 1)))()
+        lib().gmm_plan_candidates(self.handle, buf, n)
+        return [tuple(buf[3 * i: 3 * i + 3]) for i in range(n)]
+
+    def close(self):
+        if self.handle:
+            lib().gmm_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

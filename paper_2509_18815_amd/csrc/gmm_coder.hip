@@ -24,6 +24,7 @@
 #include "../../include/flashgmm.h"
 #include "gmm_device.h"
 #include "gmm_host.h"
+#include "gmm_stream.h"
 
 using namespace fgmm;
 
@@ -47,13 +48,13 @@ __global__ void k_finalize(const uint32_t* bits, int32_t* dev_status) {
   }
 }
 
-// Exhaustive check of recip_1_4 against IEEE division on every float in
+// Exhaustive check of recip_fast against IEEE division on every float in
 // [lo_bits, lo_bits + count).
 __global__ void k_recip_check(uint32_t lo_bits, uint32_t count, unsigned long long* mismatches) {
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= count) return;
   const float u = __uint_as_float(lo_bits + t);
-  const float a = recip_1_4(u);
+  const float a = recip_fast(u);
   const float b = 1.0f / u;
   if (__float_as_uint(a) != __float_as_uint(b)) atomicAdd(mismatches, 1ull);
 }
@@ -69,30 +70,8 @@ __global__ void k_cdf_table(QCfg q, int64_t n, const float* __restrict__ w,
   const int32_t j = (int32_t)(t - i * cols);
   float rw[K], rm[K], rs[K];
   load_raw<K>(w, mu, sg, n, i, rw, rm, rs);
-  const Elem<K> e = make_elem<K>(rw, rm, rs);
+  const Elem<K> e = make_elem<K, kFast>(rw, rm, rs);
   table[t] = cdf_at<K, kKind, kFast>(e, q, j);
-}
-
-// Branch-uniform binary search for the j with c_j <= slot < c_{j+1}:
-// exactly `rounds` = ceil(log2 N) evaluations; on return c_lo = c_j and
-// c_hi = c_{j+1}. Once the interval has one symbol, mid = lo re-evaluates
-// c_lo and changes nothing, so every lane runs the same instruction stream.
-template <int K, int kKind, bool kFast>
-__device__ __forceinline__ int32_t search_bs(const Elem<K>& e, const QCfg& q, int rounds,
-                                             uint32_t slot, uint32_t& c_lo, uint32_t& c_hi) {
-  int32_t lo = 0, hi = q.N;
-  c_lo = 0;
-  c_hi = q.M;
-  for (int r = 0; r < rounds; ++r) {
-    const int32_t mid = (lo + hi) >> 1;
-    const uint32_t c = cdf_at<K, kKind, kFast>(e, q, mid);
-    const bool right = slot >= c;
-    lo = right ? mid : lo;
-    c_lo = right ? c : c_lo;
-    hi = right ? hi : mid;
-    c_hi = right ? c_hi : c;
-  }
-  return lo;
 }
 
 template <int K, int kKind, bool kFast>
@@ -104,7 +83,7 @@ __global__ void k_inverse(QCfg q, int rounds, int64_t n, const float* __restrict
   if (i >= n) return;
   float rw[K], rm[K], rs[K];
   load_raw<K>(w, mu, sg, n, i, rw, rm, rs);
-  const Elem<K> e = make_elem<K>(rw, rm, rs);
+  const Elem<K> e = make_elem<K, kFast>(rw, rm, rs);
   uint32_t s = slot[i];
   if (s >= q.M) {
     atomicOr(status, kStInval);
@@ -114,8 +93,7 @@ __global__ void k_inverse(QCfg q, int rounds, int64_t n, const float* __restrict
   jout[i] = search_bs<K, kKind, kFast>(e, q, rounds, s, cl, ch);
 }
 
-// Encode phase 1: (c_j << 16) | f_j per element (both fit 16 bits: c_j <
-// M <= 2^16 for j < N and f_j <= M - N + 1 < 2^16).
+// Encode phase 1: one thread per element.
 template <int K, int kKind, bool kFast>
 __global__ void k_enc_cdf(QCfg q, int64_t n, const int32_t* __restrict__ sym,
                           const float* __restrict__ w, const float* __restrict__ mu,
@@ -123,116 +101,37 @@ __global__ void k_enc_cdf(QCfg q, int64_t n, const int32_t* __restrict__ sym,
                           uint32_t* status) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  float rw[K], rm[K], rs[K];
-  load_raw<K>(w, mu, sg, n, i, rw, rm, rs);
-  int32_t j = sym[i] - q.lo;
-  if (j < 0 || j >= q.N) {
-    atomicOr(status, kStRange);
-    j = 0;
-  }
-  const Elem<K> e = make_elem<K>(rw, rm, rs);
-  const uint32_t c0 = cdf_at<K, kKind, kFast>(e, q, j);
-  const uint32_t c1 = cdf_at<K, kKind, kFast>(e, q, j + 1);
-  cf[i] = (c0 << 16) | (c1 - c0);
+  cf[i] = enc_cdf_elem<K, kKind, kFast>(q, n, i, sym, w, mu, sg, status);
 }
 
 constexpr int kRansBlock = 256;
 
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t t = __shfl_up(v, d, 64);
-    if (lane >= d) v += t;
-  }
-  return v;
-}
-
-// Encode phase 2: one lane per stream. Stream s owns scratch words
-// [s*cap, (s+1)*cap); the k-th emitted word goes to s*cap + cap-1-k, so the
-// region's tail holds the words in the order the decoder reads them.
-// Then a block-wide exclusive scan of the segment lengths 2 + count.
+// Encode phase 2: one lane per stream; stream s owns scratch words
+// [s cap, (s+1) cap). Then the block's exclusive scan of the segment
+// lengths 2 + count (the wavefront prefix sums that place the streams).
 __global__ void __launch_bounds__(kRansBlock)
     k_enc_rans(int64_t n, int64_t S, int P, const uint32_t* __restrict__ cf,
                uint16_t* __restrict__ scratch, int64_t cap, uint32_t* __restrict__ xfin,
                uint32_t* __restrict__ count, uint32_t* __restrict__ local_off,
                int64_t* __restrict__ blk_total) {
-  __shared__ uint32_t wave_sum[kRansBlock / 64];
   const int64_t s = (int64_t)blockIdx.x * kRansBlock + threadIdx.x;
   uint32_t cnt = 0;
   if (s < S) {
-    const int64_t ns = (s < n) ? (n - 1 - s) / S + 1 : 0;
-    uint32_t x = 1u << 16;
-    uint16_t* region = scratch + s * cap + (cap - 1);
-    const int shift = 32 - P;
-    int64_t p = ns - 1;
-    uint32_t nxt = (p >= 0) ? cf[s + p * S] : 0u;
-    for (; p >= 0; --p) {
-      const uint32_t v = nxt;
-      if (p > 0) nxt = cf[s + (p - 1) * S];
-      const uint32_t c = v >> 16;
-      const uint32_t f = v & 0xFFFFu;
-      if (x >= (f << shift)) {
-        region[-(int64_t)cnt] = (uint16_t)(x & 0xFFFFu);
-        ++cnt;
-        x >>= 16;
-      }
-      const uint32_t qd = x / f;
-      x = (qd << P) + (x - qd * f) + c;
-    }
-    xfin[s] = x;
+    xfin[s] = rans_stream(n, S, P, s, cf, scratch + s * cap + (cap - 1), &cnt);
     count[s] = cnt;
   }
-  // block exclusive scan of the segment lengths
-  const uint32_t len = (s < S) ? cnt + 2u : 0u;
-  const uint32_t incl = wave_incl_scan(len);
-  const int wv = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 63) wave_sum[wv] = incl;
-  __syncthreads();
-  uint32_t base = 0;
-#pragma unroll
-  for (int k = 0; k < kRansBlock / 64; ++k) base += (k < wv) ? wave_sum[k] : 0u;
-  if (s < S) local_off[s] = base + incl - len;
-  if (threadIdx.x == kRansBlock - 1) {
-    uint32_t tot = 0;
-#pragma unroll
-    for (int k = 0; k < kRansBlock / 64; ++k) tot += wave_sum[k];
-    blk_total[blockIdx.x] = tot;
-  }
+  uint32_t tot;
+  const uint32_t excl = block_excl_scan<kRansBlock>((s < S) ? cnt + 2u : 0u, &tot);
+  if (s < S) local_off[s] = excl;
+  if (threadIdx.x == 0) blk_total[blockIdx.x] = tot;
 }
 
-// Exclusive scan of nblk int64 block totals in one workgroup of 1024
-// threads, tile by tile with a running carry.
-constexpr int kScanBlock = 1024;
 __global__ void __launch_bounds__(kScanBlock)
     k_scan_blk(int64_t nblk, const int64_t* __restrict__ tot, int64_t* __restrict__ pre) {
-  __shared__ int64_t wsum[kScanBlock / 64];
-  __shared__ int64_t carry_sh;
-  if (threadIdx.x == 0) carry_sh = 0;
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int64_t base = 0; base < nblk; base += kScanBlock) {
-    const int64_t i = base + threadIdx.x;
-    const int64_t v = (i < nblk) ? tot[i] : 0;
-    int64_t incl = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const int64_t t = __shfl_up(incl, d, 64);
-      if (lane >= d) incl += t;
-    }
-    if (lane == 63) wsum[wv] = incl;
-    __syncthreads();
-    int64_t off = carry_sh;
-    for (int k = 0; k < wv; ++k) off += wsum[k];
-    if (i < nblk) pre[i] = off + incl - v;
-    __syncthreads();
-    if (threadIdx.x == kScanBlock - 1) carry_sh = off + incl;
-    __syncthreads();
-  }
+  scan_totals(nblk, tot, pre);
 }
 
-// Offsets and compaction: 16 lanes per stream copy its segment
-// [x lo, x hi, words...] to bitstream[offsets[s] ...].
+// Offsets and compaction: 16 lanes per stream.
 constexpr int kPackBlock = 256, kPackLanes = 16;
 __global__ void __launch_bounds__(kPackBlock)
     k_pack(int64_t S, int64_t nblk, int64_t cap, const uint16_t* __restrict__ scratch,
@@ -253,65 +152,26 @@ __global__ void __launch_bounds__(kPackBlock)
     if (s == S - 1) offsets[S] = total;
   }
   if (!fits) return;
-  const uint32_t x = xfin[s];
-  const uint16_t* src = scratch + s * cap + (cap - (int64_t)cnt);
-  for (int64_t t = l; t < (int64_t)cnt + 2; t += kPackLanes) {
-    uint16_t wv;
-    if (t == 0) wv = (uint16_t)(x & 0xFFFFu);
-    else if (t == 1) wv = (uint16_t)(x >> 16);
-    else wv = src[t - 2];
-    bitstream[off + t] = wv;
-  }
+  pack_segment(bitstream + off, xfin[s], scratch + s * cap + (cap - (int64_t)cnt), cnt, l,
+               kPackLanes);
 }
 
-// Decode: one lane per stream; the next element's parameters are loaded
-// while the current symbol is searched.
-template <int K, int kKind, bool kFast>
-__global__ void __launch_bounds__(64)
+// Decode with L lanes per stream (L = 1: one lane per stream and a binary
+// search; L > 1: an (L+1)-ary search, ceil(log_{L+1} N) rounds).
+template <int K, int kKind, bool kFast, int L>
+__global__ void __launch_bounds__(256)
     k_decode(QCfg q, int P, int rounds, int64_t n, int64_t S, const uint16_t* __restrict__ bs,
              int64_t total_words, const int64_t* __restrict__ offsets,
              const float* __restrict__ w, const float* __restrict__ mu,
              const float* __restrict__ sg, int32_t* __restrict__ sym, uint32_t* status) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t s = gt / L;
+  const int g = (int)(gt % L);
+  // groups never straddle the S boundary (S * L lanes, L divides 64)
   if (s >= S) return;
-  const int64_t ns = (s < n) ? (n - 1 - s) / S + 1 : 0;
-  const int64_t a = offsets[s], b = offsets[s + 1];
-  if (a < 0 || b < a + 2 || b > total_words) {
-    for (int64_t p = 0; p < ns; ++p) sym[s + p * S] = q.lo;
-    atomicOr(status, kStCorrupt);
-    return;
-  }
-  uint32_t x = (uint32_t)bs[a] | ((uint32_t)bs[a + 1] << 16);
-  int64_t ptr = a + 2;
-  bool bad = x < (1u << 16);
-  const uint32_t mask = q.M - 1;
-  float nw[K], nm[K], nsg[K];
-  if (ns > 0) load_raw<K>(w, mu, sg, n, s, nw, nm, nsg);
-  for (int64_t p = 0; p < ns; ++p) {
-    const int64_t i = s + p * S;
-    float cw[K], cm[K], cs[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      cw[k] = nw[k];
-      cm[k] = nm[k];
-      cs[k] = nsg[k];
-    }
-    if (p + 1 < ns) load_raw<K>(w, mu, sg, n, i + S, nw, nm, nsg);
-    const Elem<K> e = make_elem<K>(cw, cm, cs);
-    const uint32_t slot = x & mask;
-    uint32_t cl, ch;
-    const int32_t j = search_bs<K, kKind, kFast>(e, q, rounds, slot, cl, ch);
-    sym[i] = q.lo + j;
-    x = (ch - cl) * (x >> P) + slot - cl;
-    if (x < (1u << 16)) {
-      uint32_t word = 0;
-      if (ptr < b) word = bs[ptr++];
-      else bad = true;
-      x = (x << 16) | word;
-    }
-  }
-  if (x != (1u << 16) || ptr != b) bad = true;
-  if (bad) atomicOr(status, kStCorrupt);
+  const bool bad = decode_stream<K, kKind, kFast, L>(q, P, rounds, n, S, s, g, bs, total_words,
+                                                     offsets, w, mu, sg, sym);
+  if (bad && g == 0) atomicOr(status, kStCorrupt);
 }
 
 // ------------------------------------------------------------- host side
@@ -374,8 +234,8 @@ int search_rounds(int32_t N) {
   return r;
 }
 
-// Per-device flag: recip_1_4 matches IEEE division on [1, 4) (checked once
-// per device, exhaustively, before the first coder launch on it).
+// Per-device flag: recip_fast matches IEEE division on [2^-10, 2^10]
+// (checked once per device, exhaustively, before the first coder launch).
 static std::mutex g_init_mu;
 static int g_fast_ok[64];  // 0 unknown, 1 verified, -1 mismatch
 
@@ -383,8 +243,8 @@ int fast_recip_mismatches(unsigned long long* count, hipStream_t st) {
   unsigned long long* d = nullptr;
   if (hipMallocAsync((void**)&d, sizeof(unsigned long long), st) != hipSuccess) return GMM_ENOMEM;
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t*)d, 0u, (int64_t)2);
-  const uint32_t lo = 0x3f800000u;        // 1.0f
-  const uint32_t cnt = 0x40800000u - lo;  // every float in [1, 4)
+  const uint32_t lo = 0x3a800000u;            // 2^-10
+  const uint32_t cnt = 0x44800000u - lo + 1;  // every float in [2^-10, 2^10]
   hipLaunchKernelGGL(k_recip_check, dim3((cnt + 255) / 256), dim3(256), 0, st, lo, cnt, d);
   unsigned long long h = 0;
   hipError_t e1 = hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, st);
@@ -457,17 +317,51 @@ int encode_launch(const gmm_cfg* cfg, int64_t n, const int32_t* symbols, const f
   return hipGetLastError() == hipSuccess ? GMM_OK : GMM_EDEVICE;
 }
 
+// Rounds of an (L+1)-ary search over N symbols: smallest R with (L+1)^R >= N.
+int search_rounds_lps(int32_t N, int L) {
+  int r = 0;
+  int64_t reach = 1;
+  while (reach < N) {
+    reach *= (L + 1);
+    ++r;
+  }
+  return r;
+}
+
+// Lanes per stream when the caller does not choose: enough lanes to give
+// the chip about 64K lanes (one wave per SIMD), at most 32 per stream.
+int default_lanes_per_stream(int64_t S) {
+  int L = 1;
+  while (L < 32 && S * L < 65536) L <<= 1;
+  return L;
+}
+
 int decode_launch(const gmm_cfg* cfg, int64_t n, const uint16_t* bs, int64_t total_words,
                   const int64_t* offsets, const float* w, const float* mu, const float* sg,
-                  int32_t* symbols, uint32_t* status, bool fast, hipStream_t st) {
+                  int32_t* symbols, uint32_t* status, bool fast, hipStream_t st, int lanes) {
   const int64_t S = cfg->num_streams;
   const QCfg q = make_qcfg(cfg);
-  const int rounds = search_rounds(q.N);
+  const int L = (lanes > 0) ? lanes : default_lanes_per_stream(S);
+  const int rounds = (L == 1) ? search_rounds(q.N) : search_rounds_lps(q.N, L);
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, status, 0u, (int64_t)1);
+  const int64_t threads = S * L;
+  const int blk = (L == 1) ? 64 : 256;
+  const dim3 grid((unsigned)((threads + blk - 1) / blk)), block(blk);
   dispatch(cfg->K, cfg->cdf_kind, fast, [&](auto Kc, auto kc, auto fc) {
-    hipLaunchKernelGGL((k_decode<decltype(Kc)::value, decltype(kc)::value, decltype(fc)::value>),
-                       dim3((unsigned)((S + 63) / 64)), dim3(64), 0, st, q, cfg->precision,
-                       rounds, n, S, bs, total_words, offsets, w, mu, sg, symbols, status);
+    constexpr int K_ = decltype(Kc)::value, KI = decltype(kc)::value;
+    constexpr bool F = decltype(fc)::value;
+#define FG_DEC(LL)                                                                             \
+  hipLaunchKernelGGL((k_decode<K_, KI, F, LL>), grid, block, 0, st, q, cfg->precision, rounds, \
+                     n, S, bs, total_words, offsets, w, mu, sg, symbols, status)
+    switch (L) {
+      case 1: FG_DEC(1); break;
+      case 2: FG_DEC(2); break;
+      case 4: FG_DEC(4); break;
+      case 8: FG_DEC(8); break;
+      case 16: FG_DEC(16); break;
+      default: FG_DEC(32); break;
+    }
+#undef FG_DEC
   });
   return hipGetLastError() == hipSuccess ? GMM_OK : GMM_EDEVICE;
 }
@@ -478,7 +372,19 @@ int64_t encode_ws_bytes(int64_t n, int64_t S) { return enc_layout(n, S).bytes; }
 
 // -------------------------------------------------------------- C ABI
 
+// Lanes per stream chosen by gmm_set_decode_lanes (0 = automatic).
+static int g_lanes_override = 0;
+
 extern "C" {
+
+int gmm_set_decode_lanes(int32_t lanes) {
+  if (lanes != 0 && lanes != 1 && lanes != 2 && lanes != 4 && lanes != 8 && lanes != 16 &&
+      lanes != 32)
+    return GMM_EINVAL;
+  g_lanes_override = lanes;
+  return GMM_OK;
+}
+
 
 const char* gmm_status_str(int s) {
   switch (s) {
@@ -604,7 +510,7 @@ int gmm_decode(const gmm_cfg* cfg, int64_t n, const uint16_t* bitstream, int64_t
     r = GMM_EINVAL;  // learned bracket not available in this build
   } else {
     r = fgmm::decode_launch(cfg, n, bitstream, total_words, offsets, w, mu, sg, symbols,
-                            (uint32_t*)wsp, fast, st);
+                            (uint32_t*)wsp, fast, st, g_lanes_override);
   }
   if (r == GMM_OK) r = fgmm::finish((uint32_t*)wsp, dev_status, st);
   if (own) (void)hipFreeAsync(wsp, st);

@@ -62,11 +62,13 @@ __device__ __forceinline__ float exp_tilde(float g) {
   return __builtin_ldexpf(p, (int)n);
 }
 
-// Correctly rounded 1/u for u in [1, 4): hardware reciprocal estimate plus
-// one fused Newton correction. Bit-equality with IEEE division over the
-// whole domain is verified exhaustively on the device (a test), so it can
-// stand in for the division the contract specifies.
-__device__ __forceinline__ float recip_1_4(float u) {
+// Correctly rounded 1/u for u in [2^-10, 2^10]: hardware reciprocal estimate
+// plus one fused Newton correction. The library checks bit-equality with
+// IEEE division on every float of that range once per device and uses this
+// form only if it holds, so it stands in for the division the contract
+// specifies (t = 1/u with u in [1, 3.09], r = 1/sigma with sigma clamped to
+// [2^-10, 2^10]).
+__device__ __forceinline__ float recip_fast(float u) {
   const float y = __builtin_amdgcn_rcpf(u);
   const float e = fma32(-u, y, 1.0f);
   return fma32(e, y, y);
@@ -77,7 +79,7 @@ __device__ __forceinline__ float recip_1_4(float u) {
 template <bool kFastRecip>
 __device__ __forceinline__ float tail_as(float a) {
   const float u = fma32(kAsP, a, 1.0f);
-  const float t = kFastRecip ? recip_1_4(u) : 1.0f / u;
+  const float t = kFastRecip ? recip_fast(u) : 1.0f / u;
   float q = fma32(kAsB5, t, kAsB4);
   q = fma32(q, t, kAsB3);
   q = fma32(q, t, kAsB2);
@@ -129,14 +131,14 @@ __device__ __forceinline__ void load_raw(const float* __restrict__ w, const floa
   }
 }
 
-template <int K>
+template <int K, bool kFastRecip>
 __device__ __forceinline__ Elem<K> make_elem(const float (&rw)[K], const float (&rm)[K],
                                              const float (&rs)[K]) {
   Elem<K> e;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const float s = __builtin_fminf(__builtin_fmaxf(rs[k], 0x1p-10f), 0x1p10f);
-    e.r[k] = 1.0f / s;
+    e.r[k] = kFastRecip ? recip_fast(s) : 1.0f / s;
     e.w[k] = (rw[k] < 0x1p-60f) ? 0.0f : rw[k];
     e.mu[k] = rm[k];
   }
@@ -167,11 +169,14 @@ __device__ __forceinline__ uint32_t cdf_inner(const Elem<K>& e, const QCfg& q, i
   return (uint32_t)j + (uint32_t)__builtin_floorf(F * q.span);
 }
 
-// c_j for any j in [0, N] (c_0 = 0, c_N = M).
+// c_j for any j in [0, N] (c_0 = 0, c_N = M). The mixture is evaluated for
+// every j and the ends are selected afterwards, so a wavefront never
+// branches on j.
 template <int K, int kKind, bool kFastRecip>
 __device__ __forceinline__ uint32_t cdf_at(const Elem<K>& e, const QCfg& q, int32_t j) {
   const uint32_t c = cdf_inner<K, kKind, kFastRecip>(e, q, j);
-  return (j <= 0) ? 0u : ((j >= q.N) ? q.M : c);
+  const uint32_t lo_end = (j <= 0) ? 0u : c;
+  return (j >= q.N) ? q.M : lo_end;
 }
 
 // Device status bits, folded into a status code by the last kernel.

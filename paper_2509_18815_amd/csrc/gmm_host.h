@@ -21,7 +21,9 @@ int encode_launch(const gmm_cfg* cfg, int64_t n, const int32_t* symbols, const f
                   int64_t* offsets, char* ws, bool fast, hipStream_t st);
 int decode_launch(const gmm_cfg* cfg, int64_t n, const uint16_t* bs, int64_t total_words,
                   const int64_t* offsets, const float* w, const float* mu, const float* sg,
-                  int32_t* symbols, uint32_t* status, bool fast, hipStream_t st);
+                  int32_t* symbols, uint32_t* status, bool fast, hipStream_t st, int lanes);
+int search_rounds_lps(int32_t N, int L);
+int default_lanes_per_stream(int64_t S);
 int decode_bracket_launch(const gmm_cfg* cfg, int64_t n, const uint16_t* bs, int64_t total_words,
                           const int64_t* offsets, const float* w, const float* mu,
                           const float* sg, int32_t* symbols, const gmm_bracket* bracket,

@@ -42,8 +42,9 @@ def gpu_roundtrip(api, cfg, sym, w, mu, sig):
 
 
 def test_fast_reciprocal_is_correctly_rounded(api):
-    """The reciprocal used for t = 1/(1 + p a) equals IEEE division on every
-    float in [1, 4) (exhaustive, on the device)."""
+    """The fused reciprocal used for t = 1/(1 + p a) and r = 1/sigma equals
+    IEEE division on every float in [2^-10, 2^10] (exhaustive, on the
+    device); if it did not, the library would use the division instead."""
     assert api.fast_recip_mismatches() == 0
 
 
@@ -116,6 +117,35 @@ def test_encode_decode_bit_exact(api, orc, n, S, K, lo, hi, P, kind):
     assert np.array_equal(off, ooff)
     assert np.array_equal(bs, obs)
     assert np.array_equal(dec, sym)
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16, 32])
+def test_decode_lanes_per_stream_bit_exact(api, orc, lanes):
+    """Every lanes-per-stream launch shape decodes the oracle's bitstream to
+    the same symbols, including ragged tails, corrupted segments and N that
+    is not a power of the search arity."""
+    rng = np.random.default_rng(lanes)
+    try:
+        for n, S, K, lo, hi, kind in [(20011, 129, 3, -255, 255, 0), (5000, 64, 5, -511, 511, 1),
+                                      (777, 1000, 2, -3, 3, 0), (40000, 300, 1, -128, 127, 0)]:
+            w, mu, sig = synth.random_params(rng, n, K)
+            sym = np.clip(np.rint(rng.normal(0, 6, size=n)), lo, hi).astype(np.int32)
+            ocfg = orc.make_cfg(K, lo, hi, 16, S, kind)
+            st, obs, ooff = orc.encode(ocfg, sym, w, mu, sig)
+            cfg = api.make_cfg(K, lo, hi, 16, S, kind)
+            api.set_decode_lanes(lanes)
+            dec = torch.empty(n, dtype=torch.int32, device="cuda")
+            dw, dm, ds = dev(w), dev(mu), dev(sig)
+            assert api.decode_into(cfg, dev(obs.view(np.int16)), dev(ooff), dw, dm, ds, dec) == 0
+            assert np.array_equal(dec.cpu().numpy(), sym)
+            flipped = obs.copy()
+            flipped[ooff[min(5, S - 1)] + 1] ^= 0x0001
+            ost, osym = orc.decode(ocfg, flipped, ooff, w, mu, sig)
+            gst = api.decode_into(cfg, dev(flipped.view(np.int16)), dev(ooff), dw, dm, ds, dec)
+            assert gst == ost
+            assert np.array_equal(dec.cpu().numpy(), osym)
+    finally:
+        api.set_decode_lanes(0)
 
 
 @pytest.mark.parametrize("name", ["c1", "c2a"])
