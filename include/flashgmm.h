@@ -119,6 +119,67 @@ typedef struct gmm_decode_stats {
   uint64_t hits, misses, wave_all_hit, wave_steps;
 } gmm_decode_stats;
 
+/* Description of a bracket model for gmm_bracket_create (all [host]).
+ * The network maps D = 3K+1 features of an element and its rANS slot —
+ * the K clamped weights, the K means, the K natural-log clamped scales and
+ * slot / 2^P, each normalised as (x - in_mean) / in_std — through
+ * D -> 64 -> ReLU -> 64 -> ReLU -> 1 to t, and predicts the symbol
+ * t * out_std + out_mean. params: float32, W1 [64][D], b1 [64], W2 [64][64],
+ * b2 [64], w3 [64], b3 [1] (rounded to bfloat16 on load). radius R: the
+ * decoder checks the bracket [p - R, p + R] around the prediction p. */
+typedef struct gmm_bracket_desc {
+  int32_t K;
+  int32_t radius;
+  const float* params;
+  const float* in_mean;
+  const float* in_std;
+  float out_mean, out_std;
+} gmm_bracket_desc;
+
+/* Uploads a bracket model (K 1..5). *out [host] receives the handle. */
+int gmm_bracket_create(const gmm_bracket_desc* desc, gmm_bracket** out);
+/* Releases a bracket model (waits for the device to be idle). */
+int gmm_bracket_destroy(gmm_bracket* bracket);
+/* Diagnostic: the model's symbol prediction for each element i at slot[i]
+ * [device, uint32 [n]] as the decoder computes it (matrix cores, bfloat16
+ * weights and inputs, float32 accumulation), into pred [device, float32
+ * [n]]. Synchronous. */
+int gmm_bracket_predict(const gmm_bracket* bracket, int32_t precision, int64_t n,
+                        const float* weights, const float* means, const float* scales,
+                        const uint32_t* slot, float* pred, void* stream);
+
+/* ---- Training of the bracket model on the GPU ----
+ * Parameter count of the D-input network (64 D + 4289). */
+int gmm_mlp_num_params(int32_t D);
+/* Device workspace bytes of gmm_mlp_loss_grad for n samples. */
+int64_t gmm_mlp_workspace_bytes(int32_t D, int64_t n);
+/* Features X [device, float32 [n][3K+1]] of element i at slot[i] [device,
+ * uint32 [n]], normalised with mean / inv_std [device, float32 [3K+1]] when
+ * given (both or neither), rounded to bfloat16 when round_bf16. K 1..5. */
+int gmm_mlp_features(int32_t K, int64_t n, const float* weights, const float* means,
+                     const float* scales, const uint32_t* slot, int32_t precision,
+                     const float* mean, const float* inv_std, int32_t round_bf16, float* X,
+                     void* stream);
+/* Sum over the n samples of the Huber loss (threshold delta) of the network
+ * output against y [device, float32 [n]] and its gradient: grad_loss
+ * [device, float32 [P + 1]] receives the P parameter gradients then the
+ * loss. params [device, float32 [P]] in the bracket layout. With round_act
+ * the first hidden layer's activations are rounded to bfloat16 (as the
+ * decoder's matrix cores see them; the gradient passes straight through).
+ * The reduction order is fixed: results are bit-reproducible. */
+int gmm_mlp_loss_grad(int32_t D, int64_t n, const float* X, const float* y, const float* params,
+                      float delta, int32_t round_act, float* grad_loss, void* ws,
+                      int64_t ws_bytes, void* stream);
+/* Network output per sample into out [device, float32 [n]]. */
+int gmm_mlp_forward(int32_t D, int64_t n, const float* X, const float* params, int32_t round_act,
+                    float* out, void* stream);
+/* One Adam step (bias-corrected, step >= 1) on float32 params with
+ * gradient grad * grad_scale; m, v are the moment buffers; shadow
+ * [device, nullable] receives the bfloat16-rounded parameters. */
+int gmm_mlp_adam(int32_t P, float* params, const float* grad, float* m, float* v, float lr,
+                 float beta1, float beta2, float eps, int32_t step, float grad_scale,
+                 float* shadow, void* stream);
+
 /* Decode n symbols [device, int32 out] from bitstream [device, uint16,
  * total_words] and offsets [device, int64, S+1] with the same parameter
  * planes and configuration used to encode. GMM_ECORRUPT if a segment lies
@@ -192,6 +253,12 @@ int gmm_plan_exec(gmm_plan* plan, const gmm_latent_io* io, int32_t* dev_status, 
 
 /* Reports the plan's chosen launch shape. */
 int gmm_plan_info(const gmm_plan* plan, gmm_plan_info_t* info);
+
+/* Decode plans only: decode with the learned bracket (NULL = plain search)
+ * and add the bracket counters to stats [device, nullable]. Drops the
+ * captured graph and the tuned shape (the next execution tunes again). The
+ * output is identical with or without the bracket. */
+int gmm_plan_set_bracket(gmm_plan* plan, const gmm_bracket* bracket, gmm_decode_stats* stats);
 
 /* Forces a launch shape (skipping the tuner) and drops the captured graph;
  * the next gmm_plan_exec captures again. lanes 1, 2, 4, 8 or 16 (decode

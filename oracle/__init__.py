@@ -65,6 +65,10 @@ def lib():
             "gmm_oracle_decode": (ctypes.c_int, [cfgp, i64, P, i64, P, P, P, P, P]),
             "gmm_oracle_inverse": (ctypes.c_int, [cfgp, i64, P, P, P, P, P]),
             "gmm_oracle_num_threads": (i32, []),
+            "gmm_oracle_mlp_num_params": (i64, [i32, i32]),
+            "gmm_oracle_mlp_forward": (None, [i32, i32, P, i64, P, P]),
+            "gmm_oracle_mlp_loss_grad": (ctypes.c_double, [i32, i32, P, i64, P, P,
+                                                           ctypes.c_double, P]),
         }
         for name, (res, args) in sigs.items():
             f = getattr(L, name)
@@ -169,3 +173,29 @@ def decode(cfg: Cfg, bitstream, offsets, w, mu, sig, n=None):
 
 def num_threads() -> int:
     return int(lib().gmm_oracle_num_threads())
+
+
+def mlp_num_params(D: int, H: int = 64) -> int:
+    return int(lib().gmm_oracle_mlp_num_params(D, H))
+
+
+def mlp_forward(params, X, H: int = 64) -> np.ndarray:
+    """FP64 forward of the bracket MLP (parameter layout W1, b1, W2, b2, w3, b3)."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    n, D = X.shape
+    assert p.size == mlp_num_params(D, H)
+    out = np.empty(n, dtype=np.float64)
+    lib().gmm_oracle_mlp_forward(D, H, _p(p), n, _p(X), _p(out))
+    return out
+
+
+def mlp_loss_grad(params, X, y, delta=1.0, H: int = 64):
+    """Sum of Huber losses and its FP64 gradient (same layout as params)."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    n, D = X.shape
+    g = np.empty_like(p)
+    loss = lib().gmm_oracle_mlp_loss_grad(D, H, _p(p), n, _p(X), _p(y), float(delta), _p(g))
+    return float(loss), g

@@ -73,6 +73,19 @@ _SIGS = {
     "gmm_plan_set_config": (ctypes.c_int, [_P, _I32, _I32, _I32]),
     "gmm_plan_candidates": (ctypes.c_int, [_P, _P, _I32]),
     "gmm_plan_destroy": (ctypes.c_int, [_P]),
+    "gmm_plan_set_bracket": (ctypes.c_int, [_P, _P, _P]),
+    "gmm_bracket_create": (ctypes.c_int, [_P, _P]),
+    "gmm_bracket_destroy": (ctypes.c_int, [_P]),
+    "gmm_bracket_predict": (ctypes.c_int, [_P, _I32, _I64, _P, _P, _P, _P, _P, _P]),
+    "gmm_mlp_num_params": (ctypes.c_int, [_I32]),
+    "gmm_mlp_workspace_bytes": (_I64, [_I32, _I64]),
+    "gmm_mlp_features": (ctypes.c_int, [_I32, _I64, _P, _P, _P, _P, _I32, _P, _P, _I32, _P, _P]),
+    "gmm_mlp_loss_grad": (ctypes.c_int, [_I32, _I64, _P, _P, _P, ctypes.c_float, _I32, _P, _P,
+                                         _I64, _P]),
+    "gmm_mlp_forward": (ctypes.c_int, [_I32, _I64, _P, _P, _I32, _P, _P]),
+    "gmm_mlp_adam": (ctypes.c_int, [_I32, _P, _P, _P, _P, ctypes.c_float, ctypes.c_float,
+                                    ctypes.c_float, ctypes.c_float, _I32, ctypes.c_float, _P,
+                                    _P]),
 }
 
 
@@ -301,6 +314,13 @@ class Plan:
         _check(lib().gmm_plan_set_config(self.handle, lanes, schedule, waves_per_cu),
                "plan_set_config")
 
+    def set_bracket(self, bracket, stats=None):
+        """Decode plans: use the learned bracket (None = plain search)."""
+        h = ctypes.c_void_p(bracket.handle if bracket is not None else 0)
+        _check(lib().gmm_plan_set_bracket(self.handle, h, _opt(stats, torch.int64, "stats")),
+               "plan_set_bracket")
+        self._bracket = bracket
+
     def candidates(self):
         n = lib().gmm_plan_candidates(self.handle, None, 0)
         buf = (ctypes.c_int32 * (3 * max(n, 1)))()
@@ -317,3 +337,101 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class BracketDesc(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int32), ("radius", ctypes.c_int32),
+                ("params", ctypes.c_void_p), ("in_mean", ctypes.c_void_p),
+                ("in_std", ctypes.c_void_p), ("out_mean", ctypes.c_float),
+                ("out_std", ctypes.c_float)]
+
+
+class Bracket:
+    """A learned search-bracket model loaded into the library (handle for
+    decode). ``params`` float32 [P], ``in_mean``/``in_std`` float32 [3K+1]."""
+
+    def __init__(self, K, params, in_mean, in_std, out_mean, out_std, radius=4):
+        import numpy as np
+        self.K, self.radius = int(K), int(radius)
+        self._keep = [np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+                      for a in (params, in_mean, in_std)]
+        d = BracketDesc(self.K, self.radius, self._keep[0].ctypes.data,
+                        self._keep[1].ctypes.data, self._keep[2].ctypes.data,
+                        float(out_mean), float(out_std))
+        h = ctypes.c_void_p(0)
+        _check(lib().gmm_bracket_create(ctypes.byref(d), ctypes.byref(h)), "bracket_create")
+        self.handle = h.value
+
+    def predict(self, precision, weights, means, scales, slot):
+        n = weights.shape[1]
+        out = torch.empty(n, dtype=torch.float32, device=weights.device)
+        w, m, s = _params(weights, means, scales, self.K)
+        _check(lib().gmm_bracket_predict(ctypes.c_void_p(self.handle), precision, n, w, m, s,
+                                         _dev(slot, torch.int32, "slot"),
+                                         ctypes.c_void_p(out.data_ptr()), _stream()),
+               "bracket_predict")
+        return out
+
+    def close(self):
+        if self.handle:
+            lib().gmm_bracket_destroy(ctypes.c_void_p(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mlp_num_params(D: int) -> int:
+    return int(lib().gmm_mlp_num_params(D))
+
+
+def mlp_features(K, weights, means, scales, slot, precision, mean=None, inv_std=None,
+                 round_bf16=False):
+    n = weights.shape[1]
+    D = 3 * K + 1
+    X = torch.empty((n, D), dtype=torch.float32, device=weights.device)
+    w, m, s = _params(weights, means, scales, K)
+    _check(lib().gmm_mlp_features(K, n, w, m, s, _dev(slot, torch.int32, "slot"), precision,
+                                  _opt(mean, torch.float32, "mean"),
+                                  _opt(inv_std, torch.float32, "inv_std"), int(round_bf16),
+                                  ctypes.c_void_p(X.data_ptr()), _stream()), "mlp_features")
+    return X
+
+
+def mlp_loss_grad(X, y, params, delta, round_act=True, ws=None):
+    """Returns a float32 device tensor [P + 1]: summed gradients, then loss."""
+    n, D = X.shape
+    P = mlp_num_params(D)
+    out = torch.empty(P + 1, dtype=torch.float32, device=X.device)
+    need = int(lib().gmm_mlp_workspace_bytes(D, n))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=X.device)
+    _check(lib().gmm_mlp_loss_grad(D, n, _dev(X, torch.float32, "X"),
+                                   _dev(y, torch.float32, "y"),
+                                   _dev(params, torch.float32, "params"), float(delta),
+                                   int(round_act), ctypes.c_void_p(out.data_ptr()),
+                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()),
+           "mlp_loss_grad")
+    return out
+
+
+def mlp_forward(X, params, round_act=True):
+    n, D = X.shape
+    out = torch.empty(n, dtype=torch.float32, device=X.device)
+    _check(lib().gmm_mlp_forward(D, n, _dev(X, torch.float32, "X"),
+                                 _dev(params, torch.float32, "params"), int(round_act),
+                                 ctypes.c_void_p(out.data_ptr()), _stream()), "mlp_forward")
+    return out
+
+
+def mlp_adam(params, grad, m, v, lr, step, grad_scale, shadow=None, beta1=0.9, beta2=0.999,
+             eps=1e-8):
+    P = params.numel()
+    _check(lib().gmm_mlp_adam(P, _dev(params, torch.float32, "params"),
+                              _dev(grad, torch.float32, "grad"), _dev(m, torch.float32, "m"),
+                              _dev(v, torch.float32, "v"), float(lr), float(beta1),
+                              float(beta2), float(eps), int(step), float(grad_scale),
+                              _opt(shadow, torch.float32, "shadow"), _stream()), "mlp_adam")

@@ -34,6 +34,7 @@
 #include "gmm_device.h"
 #include "gmm_host.h"
 #include "gmm_stream.h"
+#include "gmm_bracket_dev.h"
 
 using namespace fgmm;
 
@@ -190,6 +191,41 @@ __global__ void __launch_bounds__(64)
   }
 }
 
+// Decode with the learned bracket: work item = (latent, first stream) of 64
+// streams, one wavefront each (the matrix-core inference needs all lanes).
+template <int K, int kKind, bool kFast>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
+    kb_decode_bracket(const LatentDesc* __restrict__ desc, QCfg q, int P,
+                      const int2* __restrict__ items, int64_t n_items, int sched, uint32_t* queue,
+                      uint32_t* status, const BracketDev* __restrict__ br,
+                      unsigned long long* stats) {
+  __shared__ BracketLds lds;
+  LaneModel model;
+  load_lane_model(br, model, lds);
+  unsigned long long cnt[4] = {0, 0, 0, 0};
+  const int lane = threadIdx.x;
+  int64_t it = blockIdx.x;
+  for (;;) {
+    int64_t item;
+    if (sched == kDynamic) {
+      uint32_t v = 0;
+      if (lane == 0) v = atomicAdd(queue, 1u);
+      item = (int64_t)__shfl(v, 0, 64);
+    } else {
+      item = it;
+    }
+    if (item >= n_items) break;
+    const int2 t = items[item];
+    const LatentDesc& d = desc[t.x];
+    bracket_decode_wave<K, kKind, kFast>(q, P, d.n, d.S, (int64_t)t.y, d.bs, d.words, d.offsets,
+                                         d.w, d.mu, d.sg, d.dec, &status[t.x], br, model, lds,
+                                         cnt);
+    if (sched == kFlat) break;
+    if (sched == kStatic) it += gridDim.x;
+  }
+  bracket_flush_stats(cnt, stats);
+}
+
 __global__ void kb_finalize(const uint32_t* __restrict__ bits, int32_t B,
                             int32_t* __restrict__ codes) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -245,6 +281,9 @@ struct gmm_plan {
   int2* d_items = nullptr;
   int64_t n_items = 0;
   int32_t items_lanes = 0;
+  // learned bracket for decode (nullable) and its counters
+  const gmm_bracket* bracket = nullptr;
+  unsigned long long* stats = nullptr;
   // status
   uint32_t* d_bits = nullptr;  // [B] status bits, then the queue counter
   int32_t* d_codes = nullptr;  // [B]
@@ -334,6 +373,19 @@ int enqueue(gmm_plan* p, const Config& c, hipStream_t st) {
     hipLaunchKernelGGL(kb_pack, dim3((unsigned)p->n_pack_blk), dim3(kPBlock), 0, st, p->d_desc,
                        p->d_pack_blk, p->d_scratch, p->d_xfin, p->d_count, p->d_local,
                        p->d_blk_pre, p->d_blk_total, p->d_bits);
+  } else if (p->bracket) {
+    const int64_t grid = (c.sched == kFlat) ? p->n_items : std::min(p->n_items, persist_grid);
+    if (grid > 0) {
+      dispatch(p->cfg.K, p->cfg.cdf_kind, p->fast, [&](auto Kc, auto kc, auto fc) {
+        constexpr int K_ = decltype(Kc)::value;
+        if constexpr (K_ <= 5) {
+          hipLaunchKernelGGL((kb_decode_bracket<K_, decltype(kc)::value, decltype(fc)::value>),
+                             dim3((unsigned)grid), dim3(64), 0, st, p->d_desc, p->q,
+                             p->cfg.precision, p->d_items, p->n_items, c.sched, queue, p->d_bits,
+                             p->bracket->dev, p->stats);
+        }
+      });
+    }
   } else {
     const int L = c.lanes;
     const int rounds = (L == 1) ? search_rounds(p->q.N) : search_rounds_lps(p->q.N, L);
@@ -375,6 +427,7 @@ std::vector<Config> candidates(const gmm_plan* p) {
     int64_t streams = 0;
     for (int b = 0; b < p->B; ++b) streams += p->S[b];
     for (int L : {1, 2, 4, 8, 16}) {
+      if (p->bracket && L != 1) continue;  // the bracket kernel runs one lane per stream
       if (L > 1 && streams * L > (int64_t)p->num_cus * 64 * 64) continue;  // > 16 waves / SIMD
       v.push_back({L, kFlat, 8});
       for (int w : wpcs) {
@@ -388,8 +441,8 @@ std::vector<Config> candidates(const gmm_plan* p) {
 
 std::string shape_signature(const gmm_plan* p) {
   uint64_t h = 1469598103934665603ull;
-  const int32_t hdr[7] = {p->op, p->cfg.K, p->cfg.lo, p->cfg.hi, p->cfg.precision,
-                          p->cfg.cdf_kind, p->B};
+  const int32_t hdr[8] = {p->op, p->cfg.K, p->cfg.lo, p->cfg.hi, p->cfg.precision,
+                          p->cfg.cdf_kind, p->B, p->bracket ? 1 : 0};
   h = fnv1a(h, hdr, sizeof(hdr));
   h = fnv1a(h, p->n.data(), p->n.size() * sizeof(int64_t));
   h = fnv1a(h, p->S.data(), p->S.size() * sizeof(int64_t));
@@ -435,7 +488,7 @@ void cache_store(const std::string& sig, const Config& c, double ms) {
 
 Config default_config(const gmm_plan* p) {
   Config c;
-  if (p->op == 1) {
+  if (p->op == 1 && !p->bracket) {
     int64_t streams = 0;
     for (int b = 0; b < p->B; ++b) streams += p->S[b];
     c.lanes = default_lanes_per_stream(streams);
@@ -701,7 +754,7 @@ int gmm_plan_info(const gmm_plan* p, gmm_plan_info_t* info) {
 int gmm_plan_set_config(gmm_plan* p, int32_t lanes, int32_t schedule, int32_t waves_per_cu) {
   if (!p) return GMM_EINVAL;
   if (lanes != 1 && lanes != 2 && lanes != 4 && lanes != 8 && lanes != 16) return GMM_EINVAL;
-  if (p->op == 0 && lanes != 1) return GMM_EINVAL;
+  if ((p->op == 0 || p->bracket) && lanes != 1) return GMM_EINVAL;
   if (schedule < kFlat || schedule > kStatic || waves_per_cu < 1 || waves_per_cu > 64)
     return GMM_EINVAL;
   if (p->cap_stream) (void)hipStreamSynchronize(p->cap_stream);
@@ -719,6 +772,23 @@ int gmm_plan_set_config(gmm_plan* p, int32_t lanes, int32_t schedule, int32_t wa
     if (r) return r;
   }
   p->tuned = true;
+  return GMM_OK;
+}
+
+int gmm_plan_set_bracket(gmm_plan* p, const gmm_bracket* bracket, gmm_decode_stats* stats) {
+  if (!p || p->op != 1) return GMM_EINVAL;
+  if (bracket && (bracket->K != p->cfg.K || p->cfg.K > 5)) return GMM_EINVAL;
+  if (p->cap_stream) (void)hipStreamSynchronize(p->cap_stream);
+  (void)hipDeviceSynchronize();
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->gexec = nullptr;
+  p->graph = nullptr;
+  p->bracket = bracket;
+  p->stats = (unsigned long long*)stats;
+  p->tuned = false;
+  p->items_lanes = 0;
+  p->signature = shape_signature(p);
   return GMM_OK;
 }
 

@@ -506,8 +506,8 @@ int gmm_decode(const gmm_cfg* cfg, int64_t n, const uint16_t* bitstream, int64_t
   const bool fast = fgmm::use_fast_recip(st);
   int r;
   if (bracket) {
-    (void)stats;
-    r = GMM_EINVAL;  // learned bracket not available in this build
+    r = fgmm::decode_bracket_launch(cfg, n, bitstream, total_words, offsets, w, mu, sg, symbols,
+                                    bracket, stats, (uint32_t*)wsp, fast, st);
   } else {
     r = fgmm::decode_launch(cfg, n, bitstream, total_words, offsets, w, mu, sg, symbols,
                             (uint32_t*)wsp, fast, st, g_lanes_override);

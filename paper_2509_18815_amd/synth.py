@@ -213,3 +213,16 @@ def adversarial_params(rng, n, K):
     for i in np.nonzero(kinds == 7)[0]:
         w[0, i] = -0.5                              # outside the precondition w >= 0
     return w, mu, sig
+
+
+def random_params_torch(gen, device, n, K, s_logit=1.0, s_mu=2.0, sigma_max=20.0,
+                        sigma_min=0.11):
+    """random_params on a torch device generator: [K][n] float32 planes."""
+    import torch
+    f64 = torch.float64
+    w = torch.softmax(torch.randn((n, K), generator=gen, device=device, dtype=f64) * s_logit,
+                      dim=1).float()
+    mu = (torch.randn((n, K), generator=gen, device=device, dtype=f64) * s_mu).float()
+    lu = torch.rand((n, K), generator=gen, device=device, dtype=f64)
+    sig = torch.exp(math.log(sigma_min) + lu * (math.log(sigma_max) - math.log(sigma_min))).float()
+    return w.t().contiguous(), mu.t().contiguous(), sig.t().contiguous()
