@@ -141,8 +141,9 @@ def summarize_prof(root: str) -> str:
         kf = (kw[0], kw[1], "FETCH_SIZE")
         if kf in ctr:
             fetch_f = gib_kib / mean(ctr[kf])
-    lines = ["| kernel | grid | calls | mean us | HBM read MB | HBM write MB | "
-             "VALU instr/wave | waves | GRBM_GUI_ACTIVE |", "|---|---|---|---|---|---|---|---|---|"]
+    lines = ["| kernel | grid | calls | mean us | median us | HBM read MB | HBM write MB | "
+             "VALU instr/wave | waves | GRBM_GUI_ACTIVE |",
+             "|---|---|---|---|---|---|---|---|---|---|"]
     keys = sorted({(k[0], k[1]) for k in dur} | {(k[0], k[1]) for k in ctr},
                   key=lambda k: -mean(dur.get(k, [0])) * len(dur.get(k, [0])))
     for k in keys:
@@ -154,7 +155,8 @@ def summarize_prof(root: str) -> str:
         vi = mean(ctr.get((k[0], k[1], "SQ_INSTS_VALU"), []))
         wv = mean(ctr.get((k[0], k[1], "SQ_WAVES"), []))
         gg = mean(ctr.get((k[0], k[1], "GRBM_GUI_ACTIVE"), []))
-        lines.append(f"| {k[0]} | {k[1]} | {len(d)} | {mean(d):.2f} | {fe:.2f} | {wr:.2f} | "
+        med = sorted(d)[len(d) // 2] if d else float("nan")
+        lines.append(f"| {k[0]} | {k[1]} | {len(d)} | {mean(d):.2f} | {med:.2f} | {fe:.2f} | {wr:.2f} | "
                      f"{vi / wv if wv == wv and wv else float('nan'):.0f} | {wv:.0f} | {gg:.0f} |")
     head = [f"FETCH_SIZE scale {fetch_f:.4f}, WRITE_SIZE scale {write_f:.4f} "
             "(so that the 1 GiB calibration copy reads 1 GiB each way).", ""]
@@ -214,10 +216,11 @@ def time_events(fn, reps, stream):
     return a.elapsed_time(b) / 1e3 / reps
 
 
-def batched_form(api, synth, name, dev, reps=5):
+def batched_form(api, synth, name, dev, reps=5, bracket_model=None, loop_baseline=True):
     """One plan (hipGraph of persistent kernels, autotuned) per direction over
     a batch of uneven latents, against a loop of single-latent calls on the
-    same buffers; round trip verified."""
+    same buffers; round trip verified. With bracket_model, a second decode
+    plan with the learned bracket is measured beside the plain one."""
     import torch
     cfgd = synth.CONFIGS[name]
     lats = synth.make_latents(cfgd, backend="torch", device=dev)
@@ -249,6 +252,37 @@ def batched_form(api, synth, name, dev, reps=5):
     for L, d in zip(lats, dio):
         assert torch.equal(d["decoded"], L.symbols), "batched round trip failed"
     words = sum(int(e["offsets"][-1].item()) for e in io)
+    bracket_out = None
+    if bracket_model is not None:
+        br = bracket_model.load()
+        stats = torch.zeros(4, dtype=torch.int64, device=dev)
+        pb = api.Plan(cfgd.K, cfgd.lo, cfgd.hi, cfgd.precision, ns, Ss, op=1, autotune=True)
+        pb.set_bracket(br, stats)
+        for d in dio:
+            d["decoded"].fill_(-1)
+        assert pb.run(dio) == 0
+        for L, d in zip(lats, dio):
+            assert torch.equal(d["decoded"], L.symbols), "bracket round trip failed"
+        stats.zero_()
+        st_b = torch.zeros(len(lats), dtype=torch.int32, device=dev)
+        t_br = time_events(lambda: pb.run(dio, status=st_b), reps, stream)
+        torch.cuda.synchronize()
+        assert st_b.abs().sum().item() == 0
+        hits, misses, all_hit, steps = stats.cpu().tolist()
+        bracket_out = {"decode_sym_s": n_tot / t_br, "gain_vs_plain_decode": t_dec / t_br,
+                       "hit_rate": hits / max(hits + misses, 1),
+                       "wave_all_hit": all_hit / max(steps, 1),
+                       "decode_plan": pb.info(), "training": bracket_model.history[-2:]}
+        pb.close()
+        br.close()
+    if not loop_baseline:
+        out = {"latents": len(lats), "n": n_tot, "K": cfgd.K, "support": [cfgd.lo, cfgd.hi],
+               "encode_sym_s": n_tot / t_enc, "decode_sym_s": n_tot / t_dec,
+               "roundtrip_sym_s": n_tot / (t_enc + t_dec), "bits_per_symbol": 16.0 * words / n_tot,
+               "encode_plan": pe.info(), "decode_plan": pd.info(), "bracket": bracket_out}
+        pe.close()
+        pd.close()
+        return out
     # single-latent calls on the same buffers, for comparison
     ws = [torch.empty(api.workspace_bytes(api.make_cfg(cfgd.K, cfgd.lo, cfgd.hi, cfgd.precision,
                                                        L.streams), L.n, 0),
@@ -273,10 +307,44 @@ def batched_form(api, synth, name, dev, reps=5):
            "roundtrip_sym_s": n_tot / (t_enc + t_dec),
            "bits_per_symbol": 16.0 * words / n_tot,
            "encode_plan": pe.info(), "decode_plan": pd.info(),
-           "single_call_loop": {"encode_sym_s": n_tot / t_enc1, "decode_sym_s": n_tot / t_dec1}}
+           "single_call_loop": {"encode_sym_s": n_tot / t_enc1, "decode_sym_s": n_tot / t_dec1},
+           "bracket": bracket_out}
     pe.close()
     pd.close()
     return out
+
+
+def bracket_single_form(api, synth, dev, model, reps=5):
+    """The 4K latent (320x135x240, 65,536 streams) decoded with the plain
+    binary search and with the learned bracket, same bitstream."""
+    import torch
+    cfgd = synth.CONFIGS["c4"]
+    lat = synth.make_latents(cfgd, backend="torch", device=dev)[0]
+    L = Latent(api, cfgd, lat)
+    L.encode()
+    stream = torch.cuda.current_stream()
+    t_plain = time_events(L.decode, reps, stream)
+    br = model.load()
+    stats = torch.zeros(4, dtype=torch.int64, device=dev)
+    dec = torch.empty_like(L.dec)
+
+    def run(with_stats=False):
+        r = api.decode_into(L.cfg, L.bs, L.off, lat.weights, lat.means, lat.scales, dec,
+                            bracket=br, stats=stats if with_stats else None, ws=L.ws_dec,
+                            status=L.st[1:2])
+        assert r == 0
+    run(True)
+    torch.cuda.synchronize()
+    assert torch.equal(dec, lat.symbols), "bracket decode differs"
+    hits, misses, all_hit, steps = stats.cpu().tolist()
+    t_br = time_events(run, reps, stream)
+    torch.cuda.synchronize()
+    assert torch.equal(dec, lat.symbols) and L.st.tolist() == [0, 0]
+    br.close()
+    return {"n": L.n, "streams": L.S, "plain_decode_sym_s": L.n / t_plain,
+            "bracket_decode_sym_s": L.n / t_br, "gain": t_plain / t_br,
+            "hit_rate": hits / max(hits + misses, 1), "wave_all_hit": all_hit / max(steps, 1),
+            "training": model.history[-2:]}
 
 
 def main():
@@ -284,19 +352,22 @@ def main():
         print(summarize_prof(sys.argv[2]))
         return
     if len(sys.argv) > 2 and sys.argv[1] == "--record-traffic":
-        rec = traffic_record(sys.argv[2], "k_decode<3, 0, true>", 65536)
+        rec = traffic_record(sys.argv[2], "k_decode<3, 0, true, 1>", 65536)
         with open(TRAFFIC_FILE, "w") as fh:
             json.dump(rec, fh, indent=1)
         print(json.dumps(rec))
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="c3",
-                    help="comma list of extra forms to measure after the timed steps "
-                         "(c3: batch of 64 latents; none)")
+    ap.add_argument("--forms", default="c3,c4,c5",
+                    help="comma list of extra forms measured after the timed steps: c3 batch "
+                         "of 64 latents; c4 4K latent plain vs learned bracket; c5 batch of "
+                         "256 K=5 latents, plain vs learned bracket; none")
+    ap.add_argument("--bracket-tuples", type=int, default=10_000_000,
+                    help="training tuples of each bracket model (c4, c5)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -320,11 +391,23 @@ def main():
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
 
-    def step():
+    # HIP events around the 4K-latent decode (the dominant kernel) on the
+    # launch stream, recorded inside the timed steps
+    ev_pairs = []
+
+    def step(record=False):
         for nm in names:
             lats[nm].encode()
-        for nm in names:
-            lats[nm].decode()
+        lats["c2a"].decode()
+        if record:
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            lats["c2b"].decode()
+            b.record(stream)
+            ev_pairs.append((a, b))
+        else:
+            lats["c2b"].decode()
 
     for _ in range(args.warmup):
         step()
@@ -336,9 +419,10 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step()
+        step(record=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    dec_in_steps = sum(a.elapsed_time(b) for a, b in ev_pairs) / 1e3 / len(ev_pairs)
     for nm in names:
         lats[nm].verify()
     n_total = sum(lats[nm].n for nm in names)
@@ -366,7 +450,7 @@ def main():
                      "bits_per_symbol": 16.0 * float(L.off[-1].item()) / L.n}
     big = lats["c2b"]
     K, N = big.cfgd.K, big.cfgd.hi - big.cfgd.lo + 1
-    dec_t = ev[("c2b", "decode")]
+    dec_t = dec_in_steps
     achieved = decode_flops_per_symbol(K, N) * big.n / dec_t / 1e12
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
@@ -377,7 +461,9 @@ def main():
                 "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
                 "flops_per_symbol": decode_flops_per_symbol(K, N),
-                "launch_ms": round(dec_t * 1e3, 4)}
+                "symbols_per_launch": big.n,
+                "launch_ms": round(dec_t * 1e3, 4),
+                "launch_ms_isolated": round(ev[("c2b", "decode")] * 1e3, 4)}
     out = {
         "metric": "GMM rANS decode+encode symbols/s, bit-exact; plain vs batched+learned bracket",
         "value": value, "unit": "symbols/s", "n_gpus": 1, "steps": args.steps,
@@ -390,8 +476,23 @@ def main():
         "roofline": roofline,
         "forms": forms,
     }
-    for form in [f for f in args.forms.split(",") if f and f != "none"]:
-        forms[form + "_batched"] = batched_form(api, synth, form, dev)
+    want = [f for f in args.forms.split(",") if f and f != "none"]
+    if "c3" in want:
+        forms["c3_batched"] = batched_form(api, synth, "c3", dev)
+    if "c4" in want or "c5" in want:
+        from paper_2509_18815_amd import train
+    if "c4" in want:
+        c4 = synth.CONFIGS["c4"]
+        m4 = train.train_bracket(c4.K, c4.lo, c4.hi, c4.precision, n_train=args.bracket_tuples,
+                                 seed=synth.TRAIN_SEED_C4, device=dev)
+        forms["c4_bracket"] = bracket_single_form(api, synth, dev, m4)
+    if "c5" in want:
+        c5 = synth.CONFIGS["c5"]
+        m5 = train.train_bracket(c5.K, c5.lo, c5.hi, c5.precision, n_train=args.bracket_tuples,
+                                 seed=synth.TRAIN_SEED_C5, s_logit=c5.s_logit, s_mu=c5.s_mu,
+                                 sigma_max=c5.sigma_max, device=dev)
+        forms["c5_batched_bracket"] = batched_form(api, synth, "c5", dev, reps=3,
+                                                   bracket_model=m5, loop_baseline=False)
     if args.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB
         dst = torch.empty_like(src)

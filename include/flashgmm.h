@@ -107,6 +107,27 @@ int gmm_encode(const gmm_cfg* cfg, int64_t n, const int32_t* symbols, const floa
                int64_t capacity_words, int64_t* offsets, void* ws, int64_t ws_bytes,
                int32_t* dev_status, void* stream);
 
+/* Subset passes (the paper's two-pass Checkerboard context model, Sec. IV-A:
+ * anchors are coded first, then the other elements with parameters that
+ * the context model computes from the decoded anchors). A pass codes the m
+ * elements idx[0..m) [device, int32, each in [0, n_total)] of a latent of
+ * n_total < 2^31 elements in that order: pass position k reads element
+ * idx[k] of symbols [device, int32 [n_total]] and of the parameter planes
+ * [device, float32 [K][n_total]], belongs to stream k mod S, and decode
+ * writes only symbols[idx[k]]. The bitstream equals gmm_encode of the
+ * gathered m-element latent. An index out of range gives GMM_EINVAL (and no
+ * out-of-bounds access). Workspace as gmm_encode / gmm_decode with n = m. */
+int gmm_encode_subset(const gmm_cfg* cfg, int64_t n_total, const int32_t* idx, int64_t m,
+                      const int32_t* symbols, const float* weights, const float* means,
+                      const float* scales, uint16_t* bitstream, int64_t capacity_words,
+                      int64_t* offsets, void* ws, int64_t ws_bytes, int32_t* dev_status,
+                      void* stream);
+int gmm_decode_subset(const gmm_cfg* cfg, int64_t n_total, const int32_t* idx, int64_t m,
+                      const uint16_t* bitstream, int64_t total_words, const int64_t* offsets,
+                      const float* weights, const float* means, const float* scales,
+                      int32_t* symbols, void* ws, int64_t ws_bytes, int32_t* dev_status,
+                      void* stream);
+
 /* Bracket-search model handle (learned search seed for decode); see
  * gmm_bracket_create. NULL selects the plain binary search. */
 typedef struct gmm_bracket gmm_bracket;

@@ -74,6 +74,10 @@ _SIGS = {
     "gmm_plan_candidates": (ctypes.c_int, [_P, _P, _I32]),
     "gmm_plan_destroy": (ctypes.c_int, [_P]),
     "gmm_plan_set_bracket": (ctypes.c_int, [_P, _P, _P]),
+    "gmm_encode_subset": (ctypes.c_int, [_CFG, _I64, _P, _I64, _P, _P, _P, _P, _P, _I64, _P, _P,
+                                         _I64, _P, _P]),
+    "gmm_decode_subset": (ctypes.c_int, [_CFG, _I64, _P, _I64, _P, _I64, _P, _P, _P, _P, _P, _P,
+                                         _I64, _P, _P]),
     "gmm_bracket_create": (ctypes.c_int, [_P, _P]),
     "gmm_bracket_destroy": (ctypes.c_int, [_P]),
     "gmm_bracket_predict": (ctypes.c_int, [_P, _I32, _I64, _P, _P, _P, _P, _P, _P]),
@@ -435,3 +439,47 @@ def mlp_adam(params, grad, m, v, lr, step, grad_scale, shadow=None, beta1=0.9, b
                               _dev(v, torch.float32, "v"), float(lr), float(beta1),
                               float(beta2), float(eps), int(step), float(grad_scale),
                               _opt(shadow, torch.float32, "shadow"), _stream()), "mlp_adam")
+
+
+def checkerboard_indices(C, H, W, anchor=True, device="cuda"):
+    """Element indices (int32, latent order c*H*W + h*W + w) of the anchors
+    ((h + w) even) or of the non-anchors of a Checkerboard two-pass model."""
+    h = torch.arange(H, device=device).view(H, 1)
+    w = torch.arange(W, device=device).view(1, W)
+    sel = ((h + w) % 2 == 0) if anchor else ((h + w) % 2 == 1)
+    plane = torch.nonzero(sel.flatten(), as_tuple=False).flatten()
+    c = torch.arange(C, device=device).view(C, 1) * (H * W)
+    return (c + plane.view(1, -1)).flatten().to(torch.int32).contiguous()
+
+
+def encode_subset_into(cfg, idx, symbols, weights, means, scales, bitstream, offsets, ws=None,
+                       status=None, stream=None) -> int:
+    """Codes elements idx of the latent (symbols [n_total], planes [K][n_total])."""
+    n_total = symbols.numel()
+    w, m, s = _params(weights, means, scales, cfg.K)
+    if offsets.numel() != cfg.num_streams + 1:
+        raise ValueError("offsets must hold num_streams + 1 entries")
+    return lib().gmm_encode_subset(ctypes.byref(cfg), n_total, _dev(idx, torch.int32, "idx"),
+                                   idx.numel(), _dev(symbols, torch.int32, "symbols"), w, m, s,
+                                   _dev(bitstream, torch.int16, "bitstream"), bitstream.numel(),
+                                   _dev(offsets, torch.int64, "offsets"),
+                                   _opt(ws, torch.uint8, "ws"),
+                                   ws.numel() if ws is not None else 0,
+                                   _opt(status, torch.int32, "status"), _stream(stream))
+
+
+def decode_subset_into(cfg, idx, bitstream, offsets, weights, means, scales, symbols,
+                       total_words=None, ws=None, status=None, stream=None) -> int:
+    """Decodes a subset pass into symbols[idx] (symbols is the full latent)."""
+    n_total = symbols.numel()
+    w, m, s = _params(weights, means, scales, cfg.K)
+    if offsets.numel() != cfg.num_streams + 1:
+        raise ValueError("offsets must hold num_streams + 1 entries")
+    tw = bitstream.numel() if total_words is None else int(total_words)
+    return lib().gmm_decode_subset(ctypes.byref(cfg), n_total, _dev(idx, torch.int32, "idx"),
+                                   idx.numel(), _dev(bitstream, torch.int16, "bitstream"), tw,
+                                   _dev(offsets, torch.int64, "offsets"), w, m, s,
+                                   _dev(symbols, torch.int32, "symbols"),
+                                   _opt(ws, torch.uint8, "ws"),
+                                   ws.numel() if ws is not None else 0,
+                                   _opt(status, torch.int32, "status"), _stream(stream))

@@ -224,7 +224,8 @@ __device__ __forceinline__ void bracket_decode_wave(
       cm[k] = nm[k];
       cs[k] = nsg[k];
     }
-    if (seg_ok && p + 1 < ns) load_raw<K>(w, mu, sg, n, i + S, nw, nm, nsg);
+    if (seg_ok) load_raw<K>(w, mu, sg, n, (p + 1 < ns) ? i + S : s + (ns > 0 ? ns - 1 : 0) * S,
+                            nw, nm, nsg);
     const Elem<K> e = make_elem<K, kFast>(cw, cm, cs);
     const uint32_t slot = x & mask;
     float feat[16];
@@ -330,15 +331,12 @@ __device__ __forceinline__ void bracket_decode_wave(
       sym[i] = q.lo + lo;
       x = (c_hi - c_lo) * (x >> P) + slot - c_lo;
       if (x < (1u << 16)) {
-        if (ptr < b) {
-          x = (x << 16) | nword;
-          ++ptr;
-          nword = (ptr < b) ? bs[ptr] : 0u;
-        } else {
-          bad = true;
-          x <<= 16;
-        }
+        const bool have = ptr < b;
+        x = (x << 16) | (have ? nword : 0u);
+        bad = bad || !have;
+        ptr += have ? 1 : 0;
       }
+      nword = bs[ptr < b ? ptr : b - 1];
     }
   }
   if (seg_ok && (x != (1u << 16) || ptr != b)) bad = true;

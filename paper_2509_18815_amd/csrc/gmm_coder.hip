@@ -93,15 +93,21 @@ __global__ void k_inverse(QCfg q, int rounds, int64_t n, const float* __restrict
   jout[i] = search_bs<K, kKind, kFast>(e, q, rounds, s, cl, ch);
 }
 
-// Encode phase 1: one thread per element.
-template <int K, int kKind, bool kFast>
+// Encode phase 1: one thread per element (per pass position with kGather:
+// element idx[i] of a latent of n_total elements).
+template <int K, int kKind, bool kFast, bool kGather = false>
 __global__ void k_enc_cdf(QCfg q, int64_t n, const int32_t* __restrict__ sym,
                           const float* __restrict__ w, const float* __restrict__ mu,
                           const float* __restrict__ sg, uint32_t* __restrict__ cf,
-                          uint32_t* status) {
+                          uint32_t* status, const int32_t* __restrict__ idx = nullptr,
+                          int64_t n_total = 0) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  cf[i] = enc_cdf_elem<K, kKind, kFast>(q, n, i, sym, w, mu, sg, status);
+  if (kGather)
+    cf[i] = enc_cdf_elem<K, kKind, kFast>(q, n_total, gather_index(idx, i, n_total), sym, w, mu,
+                                           sg, status);
+  else
+    cf[i] = enc_cdf_elem<K, kKind, kFast>(q, n, i, sym, w, mu, sg, status);
 }
 
 constexpr int kRansBlock = 256;
@@ -158,20 +164,29 @@ __global__ void __launch_bounds__(kPackBlock)
 
 // Decode with L lanes per stream (L = 1: one lane per stream and a binary
 // search; L > 1: an (L+1)-ary search, ceil(log_{L+1} N) rounds).
-template <int K, int kKind, bool kFast, int L>
+template <int K, int kKind, bool kFast, int L, bool kGather = false>
 __global__ void __launch_bounds__(256)
     k_decode(QCfg q, int P, int rounds, int64_t n, int64_t S, const uint16_t* __restrict__ bs,
              int64_t total_words, const int64_t* __restrict__ offsets,
              const float* __restrict__ w, const float* __restrict__ mu,
-             const float* __restrict__ sg, int32_t* __restrict__ sym, uint32_t* status) {
+             const float* __restrict__ sg, int32_t* __restrict__ sym, uint32_t* status,
+             const int32_t* __restrict__ idx = nullptr, int64_t n_total = 0) {
   const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t s = gt / L;
   const int g = (int)(gt % L);
   // groups never straddle the S boundary (S * L lanes, L divides 64)
   if (s >= S) return;
-  const bool bad = decode_stream<K, kKind, kFast, L>(q, P, rounds, n, S, s, g, bs, total_words,
-                                                     offsets, w, mu, sg, sym);
+  const bool bad = decode_stream<K, kKind, kFast, L, kGather>(
+      q, P, rounds, n, S, s, g, bs, total_words, offsets, w, mu, sg, sym, idx, n_total);
   if (bad && g == 0) atomicOr(status, kStCorrupt);
+}
+
+// Subset (gather) pass of a latent: validates idx (every entry in
+// [0, n_total)) before the coder runs.
+__global__ void k_check_idx(const int32_t* __restrict__ idx, int64_t m, int64_t n_total,
+                            uint32_t* status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m && (idx[i] < 0 || (int64_t)idx[i] >= n_total)) atomicOr(status, kStInval);
 }
 
 // ------------------------------------------------------------- host side
@@ -286,7 +301,8 @@ int finish(uint32_t* bits, int32_t* dev_status, hipStream_t st) {
 // Encode with an explicit workspace (used by the C entry point and plans).
 int encode_launch(const gmm_cfg* cfg, int64_t n, const int32_t* symbols, const float* w,
                   const float* mu, const float* sg, uint16_t* bitstream, int64_t capacity,
-                  int64_t* offsets, char* ws, bool fast, hipStream_t st) {
+                  int64_t* offsets, char* ws, bool fast, hipStream_t st, const int32_t* idx,
+                  int64_t n_total) {
   const int64_t S = cfg->num_streams;
   const EncLayout L = enc_layout(n, S);
   const QCfg q = make_qcfg(cfg);
@@ -300,11 +316,17 @@ int encode_launch(const gmm_cfg* cfg, int64_t n, const int32_t* symbols, const f
   int64_t* blk_pre = (int64_t*)(ws + L.blk_pre);
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, status, 0u, (int64_t)1);
   if (n > 0) {
+    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    if (idx) hipLaunchKernelGGL(k_check_idx, grid, block, 0, st, idx, n, n_total, status);
     dispatch(cfg->K, cfg->cdf_kind, fast, [&](auto Kc, auto kc, auto fc) {
-      hipLaunchKernelGGL((k_enc_cdf<decltype(Kc)::value, decltype(kc)::value,
-                                    decltype(fc)::value>),
-                         dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, q, n, symbols, w,
-                         mu, sg, cf, status);
+      constexpr int K_ = decltype(Kc)::value, KI = decltype(kc)::value;
+      constexpr bool F = decltype(fc)::value;
+      if (idx)
+        hipLaunchKernelGGL((k_enc_cdf<K_, KI, F, true>), grid, block, 0, st, q, n, symbols, w,
+                           mu, sg, cf, status, idx, n_total);
+      else
+        hipLaunchKernelGGL((k_enc_cdf<K_, KI, F, false>), grid, block, 0, st, q, n, symbols, w,
+                           mu, sg, cf, status, nullptr, (int64_t)0);
     });
   }
   hipLaunchKernelGGL(k_enc_rans, dim3((unsigned)L.nblk), dim3(kRansBlock), 0, st, n, S,
@@ -338,21 +360,31 @@ int default_lanes_per_stream(int64_t S) {
 
 int decode_launch(const gmm_cfg* cfg, int64_t n, const uint16_t* bs, int64_t total_words,
                   const int64_t* offsets, const float* w, const float* mu, const float* sg,
-                  int32_t* symbols, uint32_t* status, bool fast, hipStream_t st, int lanes) {
+                  int32_t* symbols, uint32_t* status, bool fast, hipStream_t st, int lanes,
+                  const int32_t* idx, int64_t n_total) {
   const int64_t S = cfg->num_streams;
   const QCfg q = make_qcfg(cfg);
   const int L = (lanes > 0) ? lanes : default_lanes_per_stream(S);
   const int rounds = (L == 1) ? search_rounds(q.N) : search_rounds_lps(q.N, L);
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, status, 0u, (int64_t)1);
+  if (idx && n > 0)
+    hipLaunchKernelGGL(k_check_idx, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, idx, n,
+                       n_total, status);
   const int64_t threads = S * L;
   const int blk = (L == 1) ? 64 : 256;
   const dim3 grid((unsigned)((threads + blk - 1) / blk)), block(blk);
   dispatch(cfg->K, cfg->cdf_kind, fast, [&](auto Kc, auto kc, auto fc) {
     constexpr int K_ = decltype(Kc)::value, KI = decltype(kc)::value;
     constexpr bool F = decltype(fc)::value;
-#define FG_DEC(LL)                                                                             \
-  hipLaunchKernelGGL((k_decode<K_, KI, F, LL>), grid, block, 0, st, q, cfg->precision, rounds, \
-                     n, S, bs, total_words, offsets, w, mu, sg, symbols, status)
+#define FG_DEC(LL)                                                                              \
+  if (idx)                                                                                      \
+    hipLaunchKernelGGL((k_decode<K_, KI, F, LL, true>), grid, block, 0, st, q, cfg->precision,  \
+                       rounds, n, S, bs, total_words, offsets, w, mu, sg, symbols, status, idx, \
+                       n_total);                                                                \
+  else                                                                                          \
+    hipLaunchKernelGGL((k_decode<K_, KI, F, LL, false>), grid, block, 0, st, q, cfg->precision, \
+                       rounds, n, S, bs, total_words, offsets, w, mu, sg, symbols, status,      \
+                       nullptr, (int64_t)0)
     switch (L) {
       case 1: FG_DEC(1); break;
       case 2: FG_DEC(2); break;
@@ -479,7 +511,7 @@ int gmm_encode(const gmm_cfg* cfg, int64_t n, const int32_t* symbols, const floa
   }
   const bool fast = fgmm::use_fast_recip(st);
   int r = fgmm::encode_launch(cfg, n, symbols, w, mu, sg, bitstream, capacity_words, offsets,
-                              wsp, fast, st);
+                              wsp, fast, st, nullptr, 0);
   if (r == GMM_OK) r = fgmm::finish((uint32_t*)wsp, dev_status, st);
   if (own) (void)hipFreeAsync(wsp, st);
   return r;
@@ -510,8 +542,63 @@ int gmm_decode(const gmm_cfg* cfg, int64_t n, const uint16_t* bitstream, int64_t
                                     bracket, stats, (uint32_t*)wsp, fast, st);
   } else {
     r = fgmm::decode_launch(cfg, n, bitstream, total_words, offsets, w, mu, sg, symbols,
-                            (uint32_t*)wsp, fast, st, g_lanes_override);
+                            (uint32_t*)wsp, fast, st, g_lanes_override, nullptr, 0);
   }
+  if (r == GMM_OK) r = fgmm::finish((uint32_t*)wsp, dev_status, st);
+  if (own) (void)hipFreeAsync(wsp, st);
+  return r;
+}
+
+int gmm_encode_subset(const gmm_cfg* cfg, int64_t n_total, const int32_t* idx, int64_t m,
+                      const int32_t* symbols, const float* w, const float* mu, const float* sg,
+                      uint16_t* bitstream, int64_t capacity_words, int64_t* offsets, void* ws,
+                      int64_t ws_bytes, int32_t* dev_status, void* stream) {
+  int st0 = fgmm::check_cfg(cfg, m);
+  if (st0) return st0;
+  if (n_total < 0 || m > n_total || (m > 0 && (!idx || n_total > INT32_MAX))) return GMM_EINVAL;
+  if (!offsets || capacity_words < 0) return GMM_EINVAL;
+  if (m > 0 && (!symbols || !w || !mu || !sg)) return GMM_EINVAL;
+  if (capacity_words > 0 && !bitstream) return GMM_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t need = fgmm::encode_ws_bytes(m, cfg->num_streams);
+  char* wsp = (char*)ws;
+  bool own = false;
+  if (!wsp) {
+    if (hipMallocAsync((void**)&wsp, need, st) != hipSuccess) return GMM_ENOMEM;
+    own = true;
+  } else if (ws_bytes < need) {
+    return GMM_EINVAL;
+  }
+  const bool fast = fgmm::use_fast_recip(st);
+  int r = fgmm::encode_launch(cfg, m, symbols, w, mu, sg, bitstream, capacity_words, offsets,
+                              wsp, fast, st, idx, n_total);
+  if (r == GMM_OK) r = fgmm::finish((uint32_t*)wsp, dev_status, st);
+  if (own) (void)hipFreeAsync(wsp, st);
+  return r;
+}
+
+int gmm_decode_subset(const gmm_cfg* cfg, int64_t n_total, const int32_t* idx, int64_t m,
+                      const uint16_t* bitstream, int64_t total_words, const int64_t* offsets,
+                      const float* w, const float* mu, const float* sg, int32_t* symbols,
+                      void* ws, int64_t ws_bytes, int32_t* dev_status, void* stream) {
+  int st0 = fgmm::check_cfg(cfg, m);
+  if (st0) return st0;
+  if (n_total < 0 || m > n_total || (m > 0 && (!idx || n_total > INT32_MAX))) return GMM_EINVAL;
+  if (!offsets || total_words < 0) return GMM_EINVAL;
+  if (m > 0 && (!symbols || !w || !mu || !sg)) return GMM_EINVAL;
+  if (total_words > 0 && !bitstream) return GMM_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  char* wsp = (char*)ws;
+  bool own = false;
+  if (!wsp) {
+    if (hipMallocAsync((void**)&wsp, 256, st) != hipSuccess) return GMM_ENOMEM;
+    own = true;
+  } else if (ws_bytes < 256) {
+    return GMM_EINVAL;
+  }
+  const bool fast = fgmm::use_fast_recip(st);
+  int r = fgmm::decode_launch(cfg, m, bitstream, total_words, offsets, w, mu, sg, symbols,
+                              (uint32_t*)wsp, fast, st, g_lanes_override, idx, n_total);
   if (r == GMM_OK) r = fgmm::finish((uint32_t*)wsp, dev_status, st);
   if (own) (void)hipFreeAsync(wsp, st);
   return r;

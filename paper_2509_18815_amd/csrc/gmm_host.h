@@ -18,10 +18,12 @@ int finish(uint32_t* bits, int32_t* dev_status, hipStream_t st);
 int64_t encode_ws_bytes(int64_t n, int64_t S);
 int encode_launch(const gmm_cfg* cfg, int64_t n, const int32_t* symbols, const float* w,
                   const float* mu, const float* sg, uint16_t* bitstream, int64_t capacity,
-                  int64_t* offsets, char* ws, bool fast, hipStream_t st);
+                  int64_t* offsets, char* ws, bool fast, hipStream_t st,
+                  const int32_t* idx = nullptr, int64_t n_total = 0);
 int decode_launch(const gmm_cfg* cfg, int64_t n, const uint16_t* bs, int64_t total_words,
                   const int64_t* offsets, const float* w, const float* mu, const float* sg,
-                  int32_t* symbols, uint32_t* status, bool fast, hipStream_t st, int lanes);
+                  int32_t* symbols, uint32_t* status, bool fast, hipStream_t st, int lanes,
+                  const int32_t* idx = nullptr, int64_t n_total = 0);
 int search_rounds_lps(int32_t N, int L);
 int default_lanes_per_stream(int64_t S);
 int decode_bracket_launch(const gmm_cfg* cfg, int64_t n, const uint16_t* bs, int64_t total_words,

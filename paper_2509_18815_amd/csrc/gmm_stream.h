@@ -17,6 +17,15 @@ __device__ __forceinline__ int64_t stream_len(int64_t n, int64_t S, int64_t s) {
   return (s < n) ? (n - 1 - s) / S + 1 : 0;
 }
 
+// Element of a subset pass, clamped into the latent so that an invalid
+// index (reported as EINVAL by the pass's index check) never reads or
+// writes outside the buffers.
+__device__ __forceinline__ int64_t gather_index(const int32_t* __restrict__ idx, int64_t i,
+                                                int64_t n_total) {
+  const int64_t v = (int64_t)idx[i];
+  return v < 0 ? 0 : (v >= n_total ? n_total - 1 : v);
+}
+
 // Branch-uniform binary search for the j with c_j <= slot < c_{j+1}:
 // exactly `rounds` = ceil(log2 N) CDF evaluations; on return c_lo = c_j and
 // c_hi = c_{j+1}. Once the interval holds one symbol, mid = lo re-evaluates
@@ -220,7 +229,19 @@ __device__ __forceinline__ void pack_segment(uint16_t* __restrict__ dst, uint32_
 // symbols. The next element's parameters and the next renormalisation word
 // are loaded ahead of the dependent chain. Returns true if the stream fails
 // the integrity checks.
-template <int K, int kKind, bool kFast, int L>
+//
+// With kGather the coded sequence is the subset idx[0..n) of a latent of
+// n_total elements: pass position i reads its parameters at element idx[i]
+// of the [K][n_total] planes and writes its symbol to sym[idx[i]].
+// Register copy the compiler cannot coalesce away (an early-clobber output
+// never shares a register with the input).
+__device__ __forceinline__ float opaque_copy(float v) {
+  float r;
+  asm volatile("v_mov_b32 %0, %1" : "=&v"(r) : "v"(v));
+  return r;
+}
+
+template <int K, int kKind, bool kFast, int L, bool kGather = false>
 __device__ __forceinline__ bool decode_stream(const QCfg& q, int P, int rounds, int64_t n,
                                               int64_t S, int64_t s, int g,
                                               const uint16_t* __restrict__ bs, int64_t total_words,
@@ -228,7 +249,10 @@ __device__ __forceinline__ bool decode_stream(const QCfg& q, int P, int rounds, 
                                               const float* __restrict__ w,
                                               const float* __restrict__ mu,
                                               const float* __restrict__ sg,
-                                              int32_t* __restrict__ sym) {
+                                              int32_t* __restrict__ sym,
+                                              const int32_t* __restrict__ idx = nullptr,
+                                              int64_t n_total = 0) {
+  const int64_t np = kGather ? n_total : n;  // plane stride
   const int lane = threadIdx.x & 63;
   const int gbase = lane - g;
   const uint64_t gmask = (L >= 64) ? ~0ull : (((1ull << L) - 1ull) << gbase);
@@ -236,7 +260,7 @@ __device__ __forceinline__ bool decode_stream(const QCfg& q, int P, int rounds, 
   const int64_t a = offsets[s], b = offsets[s + 1];
   if (a < 0 || b < a + 2 || b > total_words) {
     if (g == 0)
-      for (int64_t p = 0; p < ns; ++p) sym[s + p * S] = q.lo;
+      for (int64_t p = 0; p < ns; ++p) sym[kGather ? gather_index(idx, s + p * S, n_total) : s + p * S] = q.lo;
     return true;
   }
   uint32_t x = (uint32_t)bs[a] | ((uint32_t)bs[a + 1] << 16);
@@ -244,37 +268,65 @@ __device__ __forceinline__ bool decode_stream(const QCfg& q, int P, int rounds, 
   uint32_t nword = (ptr < b) ? bs[ptr] : 0u;
   bool bad = x < (1u << 16);
   const uint32_t mask = q.M - 1;
-  float nw[K], nm[K], nsg[K];
-  if (ns > 0) load_raw<K>(w, mu, sg, n, s, nw, nm, nsg);
-  for (int64_t p = 0; p < ns; ++p) {
-    const int64_t i = s + p * S;
-    float cw[K], cm[K], cs[K];
+  if (ns == 0) return bad || x != (1u << 16) || ptr != b;
+  // Software pipeline over the stream's steps. Each step issues, after its
+  // own refill, first the bitstream word the next step's refill may need and
+  // then the parameters of the element kRing steps ahead into a ring of
+  // register sets. Vector loads retire in issue order, so with this order a
+  // wait for the word never waits for parameters issued after it, and the
+  // parameters get kRing - 1 whole steps to arrive. Every load is
+  // unconditional (positions past the end reload the last element or word)
+  // so the number of loads per step is fixed and the wait counts stay exact.
+  constexpr int kRing = (L == 1) ? 3 : 2;
+  const int64_t last = ns - 1;
+  auto elem_at = [&](int64_t p) -> int64_t {
+    const int64_t pp = p < last ? p : last;
+    return kGather ? gather_index(idx, s + pp * S, n_total) : s + pp * S;
+  };
+  // The first pass (p0 = -kRing) only issues the ring's first loads, so
+  // every load comes from the loop body in one fixed order.
+  float rw[kRing][K] = {}, rm[kRing][K] = {}, rs[kRing][K] = {};
+  int64_t rg[kRing] = {};
+  for (int64_t p0 = -kRing; p0 < ns; p0 += kRing) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      cw[k] = nw[k];
-      cm[k] = nm[k];
-      cs[k] = nsg[k];
-    }
-    if (p + 1 < ns) load_raw<K>(w, mu, sg, n, i + S, nw, nm, nsg);
-    const Elem<K> e = make_elem<K, kFast>(cw, cm, cs);
-    const uint32_t slot = x & mask;
-    uint32_t cl = 0, ch = q.M;
-    int32_t j;
-    if (L == 1)
-      j = search_bs<K, kKind, kFast>(e, q, rounds, slot, cl, ch);
-    else
-      j = search_group<K, kKind, kFast, L>(e, q, rounds, slot, g, gbase, gmask, 0, q.N, cl, ch);
-    if (g == 0) sym[i] = q.lo + j;
-    x = (ch - cl) * (x >> P) + slot - cl;
-    if (x < (1u << 16)) {
-      if (ptr < b) {
-        x = (x << 16) | nword;
-        ++ptr;
-        nword = (ptr < b) ? bs[ptr] : 0u;
-      } else {
-        bad = true;
-        x <<= 16;
+    for (int d = 0; d < kRing; ++d) {
+      const int64_t p = p0 + d;
+      const bool live = p >= 0 && p < ns;
+      const uint32_t slot = x & mask;
+      uint32_t cl = 0, ch = q.M;
+      if (live) {
+        // Copies that the register allocator cannot merge with the ring
+        // slot: the slot keeps one register set, and the wait for its loads
+        // lands here instead of at the loop's back edge.
+        float cw[K], cm[K], cs[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          cw[k] = opaque_copy(rw[d][k]);
+          cm[k] = opaque_copy(rm[d][k]);
+          cs[k] = opaque_copy(rs[d][k]);
+        }
+        const Elem<K> e = make_elem<K, kFast>(cw, cm, cs);
+        int32_t j;
+        if (L == 1)
+          j = search_bs<K, kKind, kFast>(e, q, rounds, slot, cl, ch);
+        else
+          j = search_group<K, kKind, kFast, L>(e, q, rounds, slot, g, gbase, gmask, 0, q.N, cl,
+                                               ch);
+        if (g == 0) sym[rg[d]] = q.lo + j;
       }
+      // State update and refill outside the branch, as selects: the word is
+      // then used on every path, which keeps its load where it is issued.
+      const uint32_t xs = (ch - cl) * (x >> P) + slot - cl;
+      const bool refill = live && xs < (1u << 16);
+      const bool have = ptr < b;
+      const uint32_t xr = refill ? ((xs << 16) | (have ? nword : 0u)) : xs;
+      x = live ? xr : x;
+      bad = bad || (refill && !have);
+      ptr += (refill && have) ? 1 : 0;
+      nword = bs[ptr < b ? ptr : b - 1];
+      asm volatile("" ::: "memory");  // keep the word's load ahead of the ring's
+      rg[d] = elem_at(p + kRing);
+      load_raw<K>(w, mu, sg, np, rg[d], rw[d], rm[d], rs[d]);
     }
   }
   return bad || x != (1u << 16) || ptr != b;

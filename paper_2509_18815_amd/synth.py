@@ -74,6 +74,7 @@ CONFIGS = {
                     channels=320, hw_range=(16, 135), s_logit=1.5, s_mu=4.0, sigma_max=40.0),
 }
 TRAIN_SEED_C4 = 6
+TRAIN_SEED_C5 = 8
 
 
 @dataclass
