@@ -201,6 +201,8 @@ def traffic_record(root: str, kernel: str, grid: int) -> dict:
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_decode_4k_320x135x240_traffic.json")
+# the dominant kernel: plain A&S decode, K=3, one lane per stream, direct indexing
+DOMINANT_KERNEL = "k_decode<3, 0, true, 1, false>"
 
 
 def time_events(fn, reps, stream):
@@ -352,7 +354,7 @@ def main():
         print(summarize_prof(sys.argv[2]))
         return
     if len(sys.argv) > 2 and sys.argv[1] == "--record-traffic":
-        rec = traffic_record(sys.argv[2], "k_decode<3, 0, true, 1>", 65536)
+        rec = traffic_record(sys.argv[2], DOMINANT_KERNEL, 65536)
         with open(TRAFFIC_FILE, "w") as fh:
             json.dump(rec, fh, indent=1)
         print(json.dumps(rec))

@@ -39,7 +39,7 @@ def build(verbose: bool = False) -> str:
 class Cfg(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int32), ("lo", ctypes.c_int32), ("hi", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("num_streams", ctypes.c_int32),
-                ("cdf_kind", ctypes.c_int32)]
+                ("cdf_kind", ctypes.c_int32), ("param_kind", ctypes.c_int32)]
 
 
 _lib = None
@@ -65,6 +65,11 @@ def lib():
             "gmm_oracle_decode": (ctypes.c_int, [cfgp, i64, P, i64, P, P, P, P, P]),
             "gmm_oracle_inverse": (ctypes.c_int, [cfgp, i64, P, P, P, P, P]),
             "gmm_oracle_num_threads": (i32, []),
+            "gmm_oracle_exp_d": (ctypes.c_double, [ctypes.c_double]),
+            "gmm_oracle_tail_ref": (ctypes.c_double, [ctypes.c_double]),
+            "gmm_oracle_phi_ref": (ctypes.c_double, [ctypes.c_double]),
+            "gmm_oracle_ref_batch": (None, [P, P, i64, i32]),
+            "gmm_oracle_params_from_raw": (ctypes.c_int, [i32, i64, P, P, P, P]),
             "gmm_oracle_mlp_num_params": (i64, [i32, i32]),
             "gmm_oracle_mlp_forward": (None, [i32, i32, P, i64, P, P]),
             "gmm_oracle_mlp_loss_grad": (ctypes.c_double, [i32, i32, P, i64, P, P,
@@ -82,8 +87,8 @@ def _p(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-def make_cfg(K, lo, hi, precision=16, num_streams=1, cdf_kind=0) -> Cfg:
-    return Cfg(K, lo, hi, precision, num_streams, cdf_kind)
+def make_cfg(K, lo, hi, precision=16, num_streams=1, cdf_kind=0, param_kind=0) -> Cfg:
+    return Cfg(K, lo, hi, precision, num_streams, cdf_kind, param_kind)
 
 
 def _params(w, mu, sig):
@@ -99,6 +104,26 @@ def phi(z, kind=0) -> np.ndarray:
     out = np.empty_like(z)
     lib().gmm_oracle_phi_batch(_p(z), _p(out), z.size, kind)
     return out
+
+
+def ref_batch(x, which: str) -> np.ndarray:
+    """binary64 reference functions over an array: 'exp' (exp of g in
+    [-686, 0]), 'tail' (Q(a) = erfc(a/sqrt 2)/2, a in [0, 37]) or 'phi'."""
+    x = np.ascontiguousarray(x, dtype=np.float64).ravel()
+    out = np.empty_like(x)
+    lib().gmm_oracle_ref_batch(_p(x), _p(out), x.size, {"exp": 0, "tail": 1, "phi": 2}[which])
+    return out
+
+
+def params_from_raw(logits, log_scales):
+    """Raw outputs [K][n] (weight logits, log-scales) -> (weights, scales)."""
+    l = np.ascontiguousarray(logits, dtype=np.float32)
+    t = np.ascontiguousarray(log_scales, dtype=np.float32)
+    assert l.shape == t.shape and l.ndim == 2
+    w, sg = np.empty_like(l), np.empty_like(t)
+    st = lib().gmm_oracle_params_from_raw(l.shape[0], l.shape[1], _p(l), _p(t), _p(w), _p(sg))
+    assert st == OK, st
+    return w, sg
 
 
 def exp(g) -> np.ndarray:

@@ -18,8 +18,15 @@
  *     mod(x, l_s) with m = 2^P, l_s = the symbol's frequency, b_s = its
  *     cumulative frequency.
  *   - Sec. III-B: the Gaussian CDF is replaced by a closed-form approximation:
- *     the Abramowitz & Stegun 26.2.17 polynomial (default) or the logistic
- *     function 1/(1+exp(-1.702 x)).
+ *     the Abramowitz & Stegun 26.2.17 polynomial (default), the logistic
+ *     function 1/(1+exp(-1.702 x)) or Polya's formula; Table II compares
+ *     them with an unapproximated erfc, for which cdf_kind 3 evaluates the
+ *     Gaussian CDF in binary64 from the Maclaurin series of erf and the
+ *     Laplace continued fraction of erfc.
+ *   - Sec. I and II-A: the mixture parameters come from a network; with
+ *     param_kind 1 the inputs are its raw outputs (weight logits, means,
+ *     log-scales), mapped here by a softmax and an exponential with the
+ *     scale lower bound 0.11 that Sec. II-C quotes for scale tables.
  * The paper fixes no float format, rANS word size, stream layout or CDF
  * quantization; the readings taken here (binary32 with a fixed operation
  * order, 32-bit state with 16-bit renormalisation, round-robin interleaved
@@ -58,10 +65,34 @@ static const float INV_FACT4 = 0x1.555556p-5f;  /* 1/4! */
 static const float INV_FACT5 = 0x1.111112p-7f;  /* 1/5! */
 static const float INV_FACT6 = 0x1.6c16c2p-10f; /* 1/6! */
 static const float INV_FACT7 = 0x1.a01a02p-13f; /* 1/7! */
+static const float INV_FACT8 = 0x1.a01a02p-16f; /* 1/8! */
+/* Polya: Phi(x) ~ (1 + sign(x) sqrt(1 - exp(-2 x^2 / pi))) / 2 */
+static const float POLYA_C = 0x1.45f306p-1f; /* 2/pi */
+/* raw-output mapping: scale lower bound and clamps */
+static const float SCALE_MIN = 0x1.c28f5cp-4f; /* 0.11 */
 
-/* exp(g) for g in [-40.5, 0]: n = rint(g / ln 2), r = g - n ln 2 (two fused
- * steps, exact high part), then the Taylor polynomial sum_{k<=7} r^k / k!
- * by Horner, scaled by 2^n. */
+/* binary64 reference CDF (cdf_kind 3): each the binary64 value nearest the
+ * stated real; LN2_HI_D keeps 42 significant bits of ln 2, so n * LN2_HI_D
+ * is exact for |n| < 2^11. */
+static const double LOG2E_D = 0x1.71547652b82fep+0;
+static const double LN2_HI_D = 0x1.62e42fefa38p-1;
+static const double LN2_LO_D = 0x1.ef35793c7673p-45;
+static const double INV_SQRT2_D = 0x1.6a09e667f3bcdp-1;     /* 1/sqrt(2) */
+static const double INV_SQRT_PI_D = 0x1.20dd750429b6dp-1;   /* 1/sqrt(pi) */
+static const double HALF_INV_SQRT_PI_D = 0x1.20dd750429b6dp-2; /* 1/(2 sqrt(pi)) */
+/* 1/k! for k = 0..13 */
+static const double INV_FACT_D[14] = {
+    1.0, 1.0, 0x1p-1, 0x1.5555555555555p-3, 0x1.5555555555555p-5, 0x1.1111111111111p-7,
+    0x1.6c16c16c16c17p-10, 0x1.a01a01a01a01ap-13, 0x1.a01a01a01a01ap-16,
+    0x1.71de3a556c734p-19, 0x1.27e4fb7789f5cp-22, 0x1.ae64567f544e4p-26,
+    0x1.1eed8eff8d898p-29, 0x1.6124613a86d09p-33};
+#define ERF_TERMS 32  /* Maclaurin terms of erf(x), used for x < 2 */
+#define ERFC_CF_DEPTH 50 /* Laplace continued-fraction levels, x >= 2 */
+
+/* exp(g) for g in [-51.6, 7] (the range the contract uses; the result is a
+ * normal float): n = rint(g / ln 2), r = g - n ln 2 (two fused steps, exact
+ * high part), then the Taylor polynomial sum_{k<=7} r^k / k! by Horner,
+ * scaled by 2^n. */
 float gmm_oracle_exp(float g) {
   float n = rintf(g * LOG2E);
   float r = fmaf(-n, LN2_HI, g);
@@ -102,20 +133,111 @@ static float tail_logistic(float a) {
   return e / (1.0f + e);
 }
 
+/* Upper tail of Polya's approximation for a >= 0,
+ *   T(a) = (1 - sqrt(1 - exp(-u))) / 2 = (exp(-u)/2) / (1 + sqrt(E)),
+ *   u = (2/pi) a^2, E = 1 - exp(-u) = -expm1(-u),
+ * in the rationalised form, so neither end cancels: E comes from its Taylor
+ * series u (1 - u/2! + u^2/3! - ... - u^7/8!) for u < 1/4 and from
+ * 1 - exp~(-u) above. T moves with e = exp~(-u) and against E, each step
+ * being a correctly rounded monotone operation. */
+float gmm_oracle_polya_E(float u) {
+  float g = -u;
+  if (u < 0.25f) {
+    float p = INV_FACT8;
+    p = fmaf(p, g, INV_FACT7);
+    p = fmaf(p, g, INV_FACT6);
+    p = fmaf(p, g, INV_FACT5);
+    p = fmaf(p, g, INV_FACT4);
+    p = fmaf(p, g, INV_FACT3);
+    p = fmaf(p, g, 0.5f);
+    p = fmaf(p, g, 1.0f);
+    return u * p;
+  }
+  return 1.0f - gmm_oracle_exp(g);
+}
+
+static float tail_polya(float a) {
+  float m = a * a;
+  float u = m * POLYA_C;
+  float e = gmm_oracle_exp(-u);
+  float E = gmm_oracle_polya_E(u);
+  float s = sqrtf(E);
+  float h = e * 0.5f;
+  return h / (1.0f + s);
+}
+
+/* exp(g) in binary64 for g in [-686, 0] (result normal): n = rint(g/ln 2),
+ * r = g - n ln 2 in two fused steps, Taylor polynomial of degree 13 by
+ * Horner (|r| <= 0.35, truncation below 2^-57), times 2^n. */
+double gmm_oracle_exp_d(double g) {
+  double n = rint(g * LOG2E_D);
+  double r = fma(-n, LN2_HI_D, g);
+  r = fma(-n, LN2_LO_D, r);
+  double p = INV_FACT_D[13];
+  for (int k = 12; k >= 0; --k) p = fma(p, r, INV_FACT_D[k]);
+  return ldexp(p, (int)n);
+}
+
+/* Upper Gaussian tail Q(a) = erfc(a / sqrt 2) / 2 for a in [0, 37], binary64.
+ * With x = a / sqrt 2 and y = x^2:
+ *   x < 2:  erf(x) = (2/sqrt pi) x sum_{n>=0} (-y)^n / (n! (2n+1))  (Maclaurin
+ *           series), the sum nested as s_{n-1} = 1/(2n-1) - (y/n) s_n from
+ *           s_N = 1/(2N+1); Q = 1/2 - x s / sqrt pi;
+ *   x >= 2: erfc(x) = exp(-y) / sqrt(pi) / (x + (1/2)/(x + 1/(x + (3/2)/(x +
+ *           ...)))) (Laplace's continued fraction), evaluated bottom-up
+ *           from a fixed depth; Q = exp(-y) / (2 sqrt pi) / u.
+ * Relative error below 1e-12 on [0, 37] (series cancellation near x = 2 is
+ * the largest term), far under the 7.5e-8 of A&S 26.2.17. */
+double gmm_oracle_tail_ref(double a) {
+  double x = a * INV_SQRT2_D;
+  double y = x * x;
+  if (x < 2.0) {
+    double s = 1.0 / (2 * ERF_TERMS + 1);
+    for (int n = ERF_TERMS; n >= 1; --n) {
+      double v = y * (1.0 / n);
+      s = fma(-v, s, 1.0 / (2 * n - 1));
+    }
+    double t1 = x * s;
+    return fma(-INV_SQRT_PI_D, t1, 0.5);
+  }
+  double u = x;
+  for (int m = ERFC_CF_DEPTH; m >= 1; --m) u = x + (0.5 * m) / u;
+  double e = gmm_oracle_exp_d(-y);
+  double t2 = e * HALF_INV_SQRT_PI_D;
+  return t2 / u;
+}
+
+/* Reference Gaussian CDF, binary64: z clamped to [-37, 37] (so exp stays
+ * normal); Phi(-a) = Q(a), Phi(a) = 1 - Q(a). */
+double gmm_oracle_phi_ref(double z) {
+  z = fmin(fmax(z, -37.0), 37.0);
+  double a = fabs(z);
+  double q = gmm_oracle_tail_ref(a);
+  return (z < 0.0) ? q : 1.0 - q;
+}
+
 /* Phi~(z): clamp z to [-9, 9]; Phi(-a) = tail(a) and Phi(a) = 1 - tail(a).
  * The float A&S tail slightly exceeds 1/2 for tiny a (its coefficients sum
  * to just over sqrt(pi/2) after rounding), which would make Phi~ step down
  * across z = 0; capping the tail at 1/2 keeps Phi~ non-decreasing there. */
 float gmm_oracle_phi(float z, int32_t kind) {
+  if (kind == 3) return (float)gmm_oracle_phi_ref((double)z);
   z = fminf(fmaxf(z, -9.0f), 9.0f);
   float a = fabsf(z);
-  float tail = (kind == 1) ? tail_logistic(a) : tail_as(a);
+  float tail = (kind == 1) ? tail_logistic(a) : (kind == 2) ? tail_polya(a) : tail_as(a);
   tail = fminf(tail, 0.5f);
   return (z < 0.0f) ? tail : 1.0f - tail;
 }
 
 void gmm_oracle_phi_batch(const float* z, float* out, int64_t n, int32_t kind) {
   for (int64_t i = 0; i < n; ++i) out[i] = gmm_oracle_phi(z[i], kind);
+}
+
+void gmm_oracle_ref_batch(const double* x, double* out, int64_t n, int32_t which) {
+  for (int64_t i = 0; i < n; ++i)
+    out[i] = (which == 0) ? gmm_oracle_exp_d(x[i])
+             : (which == 1) ? gmm_oracle_tail_ref(x[i])
+                            : gmm_oracle_phi_ref(x[i]);
 }
 
 void gmm_oracle_exp_batch(const float* g, float* out, int64_t n) {
@@ -136,7 +258,8 @@ static int check_cfg(const gmm_oracle_cfg* c, int64_t n) {
   if (c->K < 1 || c->K > 8) return ORC_EINVAL;
   if (c->precision < 2 || c->precision > 16) return ORC_EINVAL;
   if (c->num_streams < 1) return ORC_EINVAL;
-  if (c->cdf_kind != 0 && c->cdf_kind != 1) return ORC_EINVAL;
+  if (c->cdf_kind < 0 || c->cdf_kind > 3) return ORC_EINVAL;
+  if (c->param_kind != 0 && c->param_kind != 1) return ORC_EINVAL;
   if (c->lo < -(1 << 22) || c->hi > (1 << 22) || c->hi <= c->lo) return ORC_EINVAL;
   int64_t N = (int64_t)c->hi - c->lo + 1;
   int64_t M = (int64_t)1 << c->precision;
@@ -144,19 +267,69 @@ static int check_cfg(const gmm_oracle_cfg* c, int64_t n) {
   return ORC_OK;
 }
 
+/* Raw network outputs of one element to mixture weights and scales:
+ *   weights: softmax of the logits l_k, as m = max_k l_k (in component
+ *            order), e_k = exp~(max(l_k - m, -40.5)), s = e_0 + e_1 + ...
+ *            (in order), w_k = e_k / s;
+ *   scales:  sigma_k = max(exp~(min(max(t_k, -7), 7)), 0.11) from the
+ *            log-scale t_k. */
+static void raw_to_params(int K, const float* l, const float* t, float* w, float* sg) {
+  float m = l[0];
+  for (int k = 1; k < K; ++k) m = fmaxf(m, l[k]);
+  float e[8] = {0};
+  for (int k = 0; k < K; ++k) e[k] = gmm_oracle_exp(fmaxf(l[k] - m, -40.5f));
+  float s = e[0];
+  for (int k = 1; k < K; ++k) s = s + e[k];
+  for (int k = 0; k < K; ++k) w[k] = e[k] / s;
+  for (int k = 0; k < K; ++k)
+    sg[k] = fmaxf(gmm_oracle_exp(fminf(fmaxf(t[k], -7.0f), 7.0f)), SCALE_MIN);
+}
+
+int gmm_oracle_params_from_raw(int32_t K, int64_t n, const float* logits,
+                               const float* log_scales, float* w_out, float* sigma_out) {
+  if (K < 1 || K > 8 || n < 0) return ORC_EINVAL;
+  for (int64_t i = 0; i < n; ++i) {
+    float l[8], t[8], w[8], sg[8];
+    for (int k = 0; k < K; ++k) {
+      l[k] = logits[(int64_t)k * n + i];
+      t[k] = log_scales[(int64_t)k * n + i];
+    }
+    raw_to_params(K, l, t, w, sg);
+    for (int k = 0; k < K; ++k) {
+      w_out[(int64_t)k * n + i] = w[k];
+      sigma_out[(int64_t)k * n + i] = sg[k];
+    }
+  }
+  return ORC_OK;
+}
+
 /* One element's parameters after the per-element clamps: scale to
- * [2^-10, 2^10] and its reciprocal, weights below 2^-60 to zero. */
+ * [2^-10, 2^10] (kept in s) and its reciprocal r, weights below 2^-60 to
+ * zero. With param_kind 1 the planes hold raw outputs, mapped first. */
 typedef struct {
-  float w[8], mu[8], r[8];
+  float w[8], mu[8], r[8], s[8];
 } elem_params;
 
 static void load_elem(const gmm_oracle_cfg* c, int64_t n, int64_t i, const float* w,
                       const float* mu, const float* sig, elem_params* e) {
+  float wv[8], sv[8];
   for (int k = 0; k < c->K; ++k) {
-    float s = fminf(fmaxf(sig[(int64_t)k * n + i], 0x1p-10f), 0x1p10f);
+    wv[k] = w[(int64_t)k * n + i];
+    sv[k] = sig[(int64_t)k * n + i];
+  }
+  if (c->param_kind == 1) {
+    float l[8], t[8];
+    for (int k = 0; k < c->K; ++k) {
+      l[k] = wv[k];
+      t[k] = sv[k];
+    }
+    raw_to_params(c->K, l, t, wv, sv);
+  }
+  for (int k = 0; k < c->K; ++k) {
+    float s = fminf(fmaxf(sv[k], 0x1p-10f), 0x1p10f);
+    e->s[k] = s;
     e->r[k] = 1.0f / s;
-    float wk = w[(int64_t)k * n + i];
-    e->w[k] = (wk < 0x1p-60f) ? 0.0f : wk;
+    e->w[k] = (wv[k] < 0x1p-60f) ? 0.0f : wv[k];
     e->mu[k] = mu[(int64_t)k * n + i];
   }
 }
@@ -173,17 +346,35 @@ static float mixture_F(const gmm_oracle_cfg* c, const elem_params* e, int64_t j)
   return fminf(F, 1.0f);
 }
 
+/* The same mixture in binary64 with the reference CDF (cdf_kind 3):
+ * z_k = (b - mu_k) / sigma_k with a binary64 division. */
+static double mixture_F_ref(const gmm_oracle_cfg* c, const elem_params* e, int64_t j) {
+  double b = (double)(c->lo + j) - 0.5;
+  double F = 0.0;
+  for (int k = 0; k < c->K; ++k) {
+    double z = (b - (double)e->mu[k]) / (double)e->s[k];
+    F = fma((double)e->w[k], gmm_oracle_phi_ref(z), F);
+  }
+  return fmin(F, 1.0);
+}
+
 /* Quantized CDF column: c_0 = 0, c_N = M, and for 0 < j < N
- * c_j = j + floor(F_j (M - N)), which is strictly increasing (every symbol
- * keeps frequency >= 1) because F_j does not decrease with j. */
+ * c_j = j + floor(F_j (M - N)) (in binary64 for cdf_kind 3), which is
+ * strictly increasing (every symbol keeps frequency >= 1) because F_j does
+ * not decrease with j. */
 static void build_column(const gmm_oracle_cfg* c, const elem_params* e, uint32_t* col) {
   int64_t N = (int64_t)c->hi - c->lo + 1;
   uint32_t M = 1u << c->precision;
   float span = (float)(M - (uint32_t)N);
   col[0] = 0;
   for (int64_t j = 1; j < N; ++j) {
-    float F = mixture_F(c, e, j);
-    col[j] = (uint32_t)j + (uint32_t)floorf(F * span);
+    if (c->cdf_kind == 3) {
+      double F = mixture_F_ref(c, e, j);
+      col[j] = (uint32_t)j + (uint32_t)floor(F * (double)(M - (uint32_t)N));
+    } else {
+      float F = mixture_F(c, e, j);
+      col[j] = (uint32_t)j + (uint32_t)floorf(F * span);
+    }
   }
   col[N] = M;
 }
@@ -197,7 +388,9 @@ int gmm_oracle_F_table(const gmm_oracle_cfg* c, int64_t n, const float* w, const
   for (int64_t i = 0; i < n; ++i) {
     elem_params e;
     load_elem(c, n, i, w, mu, sig, &e);
-    for (int64_t j = 0; j <= N; ++j) out[i * (N + 1) + j] = mixture_F(c, &e, j);
+    for (int64_t j = 0; j <= N; ++j)
+      out[i * (N + 1) + j] =
+          (c->cdf_kind == 3) ? (float)mixture_F_ref(c, &e, j) : mixture_F(c, &e, j);
   }
   return ORC_OK;
 }

@@ -28,13 +28,29 @@ typedef struct {
   int32_t lo, hi;      /* alphabet = the integers lo..hi, N = hi-lo+1 */
   int32_t precision;   /* P: frequencies sum to M = 2^P, 2 <= P <= 16 */
   int32_t num_streams; /* S interleaved rANS streams, S >= 1 */
-  int32_t cdf_kind;    /* 0: A&S 26.2.17 Gaussian CDF; 1: logistic CDF */
+  int32_t cdf_kind;    /* 0: A&S 26.2.17; 1: logistic; 2: Polya;
+                          3: binary64 reference (series / continued fraction) */
+  int32_t param_kind;  /* 0: weights, means, scales; 1: raw outputs (weight
+                          logits, means, log-scales) mapped per element */
 } gmm_oracle_cfg;
 
 /* Gaussian CDF approximation Phi~(z), binary32 contract arithmetic. */
 float gmm_oracle_phi(float z, int32_t kind);
-/* exp~(g) for g in [-40.5, 0]: Cody-Waite reduction + degree-7 Taylor. */
+/* exp~(g) for g in [-51.6, 7]: Cody-Waite reduction + degree-7 Taylor. */
 float gmm_oracle_exp(float g);
+/* binary64 exp for g in [-686, 0]; reference Gaussian tail Q(a) = erfc(a/sqrt2)/2
+ * for a in [0, 37]; reference Phi(z) (z clamped to [-37, 37]). */
+/* Polya's 1 - exp(-u) for u in [0, 51.6] (Taylor series below 1/4). */
+float gmm_oracle_polya_E(float u);
+double gmm_oracle_exp_d(double g);
+double gmm_oracle_tail_ref(double a);
+double gmm_oracle_phi_ref(double z);
+/* which: 0 exp, 1 tail, 2 phi (the three binary64 functions above). */
+void gmm_oracle_ref_batch(const double* x, double* out, int64_t n, int32_t which);
+/* Raw network outputs to weights and scales (planes [K][n]): softmax of the
+ * logits, sigma = max(exp~(clamp(t, -7, 7)), 0.11) of the log-scales. */
+int gmm_oracle_params_from_raw(int32_t K, int64_t n, const float* logits,
+                               const float* log_scales, float* w_out, float* sigma_out);
 void gmm_oracle_phi_batch(const float* z, float* out, int64_t n, int32_t kind);
 void gmm_oracle_exp_batch(const float* g, float* out, int64_t n);
 

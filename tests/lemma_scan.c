@@ -68,3 +68,62 @@ void lemma_scan(uint32_t lo_bits, uint32_t hi_bits, int kind, double* out) {
   out[2] = arg;
   out[3] = min_tail;
 }
+
+float gmm_oracle_exp(float g);
+
+static float f_of(uint32_t bits) {
+  float a;
+  memcpy(&a, &bits, 4);
+  return a;
+}
+
+/* Scan behind the Polya lemma, over every float u in [0, u(hi_bits)] with
+ * g = -u: out[0] = max relative error of exp~(g) against binary64 exp(g);
+ * out[1] = min of exp~(g) over u <= ua; out[2] = max of exp~(g) over
+ * u >= ub. */
+void polya_exp_scan(uint32_t hi_bits, double ua, double ub, double* out) {
+  double eps = 0.0, mn = 2.0, mx = 0.0;
+#pragma omp parallel for schedule(static, 1 << 16) reduction(max : eps, mx) reduction(min : mn)
+  for (int64_t b = 0; b <= (int64_t)hi_bits; ++b) {
+    const float u = f_of((uint32_t)b);
+    const float e = gmm_oracle_exp(-u);
+    const double ref = exp(-(double)u);
+    const double rel = fabs((double)e - ref) / ref;
+    if (rel > eps) eps = rel;
+    if ((double)u <= ua && e < mn) mn = e;
+    if ((double)u >= ub && e > mx) mx = e;
+  }
+  out[0] = eps;
+  out[1] = mn;
+  out[2] = mx;
+}
+
+float gmm_oracle_polya_E(float u);
+
+/* Polya's E = 1 - exp(-u) over every float u in [0, u(hi_bits)]: the
+ * largest relative error against binary64 -expm1(-u). */
+double polya_E_scan(uint32_t hi_bits) {
+  double eta = 0.0;
+#pragma omp parallel for schedule(static, 1 << 16) reduction(max : eta)
+  for (int64_t b = 1; b <= (int64_t)hi_bits; ++b) {
+    const float u = f_of((uint32_t)b);
+    const double ref = -expm1(-(double)u);
+    const double rel = fabs((double)gmm_oracle_polya_E(u) - ref) / ref;
+    if (rel > eta) eta = rel;
+  }
+  return eta;
+}
+
+/* The float tail Phi~(-a) of a CDF kind over every float a in
+ * [0, a(hi_bits)]: out[0] = largest, out[1] = smallest value. */
+void tail_range_scan(uint32_t hi_bits, int kind, double* out) {
+  double mx = 0.0, mn = 1.0;
+#pragma omp parallel for schedule(static, 1 << 16) reduction(max : mx) reduction(min : mn)
+  for (int64_t b = 0; b <= (int64_t)hi_bits; ++b) {
+    const float t = gmm_oracle_phi(-f_of((uint32_t)b), kind);
+    if (t > mx) mx = t;
+    if (t < mn) mn = t;
+  }
+  out[0] = mx;
+  out[1] = mn;
+}

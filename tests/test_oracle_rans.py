@@ -100,7 +100,8 @@ def test_error_codes(orc):
     for bad in [orc.make_cfg(0, -32, 31, 16, 7), orc.make_cfg(9, -32, 31, 16, 7),
                 orc.make_cfg(K, -32, 31, 1, 7), orc.make_cfg(K, -32, 31, 17, 7),
                 orc.make_cfg(K, -32, 31, 16, 0), orc.make_cfg(K, 5, 5, 16, 7),
-                orc.make_cfg(K, -32, 31, 6, 7), orc.make_cfg(K, -32, 31, 16, 7, 2)]:
+                orc.make_cfg(K, -32, 31, 6, 7), orc.make_cfg(K, -32, 31, 16, 7, 4),
+                orc.make_cfg(K, -32, 31, 16, 7, -1), orc.make_cfg(K, -32, 31, 16, 7, 0, 2)]:
         assert orc.encode(bad, sym, w, mu, sig)[0] == orc.EINVAL
     # out-of-support symbol
     s2 = sym.copy()
