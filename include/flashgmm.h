@@ -57,13 +57,25 @@ extern "C" {
  *              |lo|, |hi| <= 2^22
  *  precision   P, 2..16: quantized frequencies sum to M = 2^P
  *  num_streams S >= 1 interleaved rANS streams
- *  cdf_kind    0 = A&S 26.2.17 Gaussian CDF, 1 = logistic CDF (Sec. III-B) */
+ *  cdf_kind    Gaussian CDF used inside the mixture (Sec. III-B, Table II):
+ *              0 = A&S 26.2.17, 1 = logistic 1/(1+exp(-1.702 z)),
+ *              2 = Polya (1 + sign(z) sqrt(1 - exp(-2 z^2/pi)))/2,
+ *              3 = binary64 reference (erf series / erfc continued
+ *              fraction, error below 1e-12). Kinds 2 and 3 are built for
+ *              gmm_encode, gmm_decode without bracket, gmm_cdf_table and
+ *              gmm_inverse_cdf (decode with 1 or 16 lanes per stream);
+ *              plans and subset passes take kinds 0 and 1.
+ *  param_kind  0 = the planes hold weights, means, scales; 1 = they hold a
+ *              network's raw outputs (weight logits, means, log-scales),
+ *              mapped per element inside the coder kernels exactly as
+ *              gmm_params_from_raw maps them (no bracket with 1). */
 typedef struct gmm_cfg {
   int32_t K;
   int32_t lo, hi;
   int32_t precision;
   int32_t num_streams;
   int32_t cdf_kind;
+  int32_t param_kind;
 } gmm_cfg;
 
 /* Human-readable name of a status code (static string). */
@@ -308,6 +320,17 @@ int gmm_set_decode_lanes(int32_t lanes);
  * reciprocal differs from IEEE division (*count [host]); the library uses
  * the fused form on a device only when this is 0. Synchronous. */
 int gmm_fast_recip_mismatches(uint64_t* count, void* stream);
+
+/* Raw network outputs to mixture parameters, one element per thread (the
+ * entropy parameters come from a network, Sec. I and II-A; the scale lower
+ * bound 0.11 is the one Sec. II-C quotes for scale tables). Planes [K][n]
+ * [device]: weights = softmax over k of logits (differences to the largest
+ * logit floored at -40.5, exp~ of the binary32 contract, sum in component
+ * order, IEEE division); scales = max(exp~(clamp(log_scales, -7, 7)), 0.11).
+ * Asynchronous on stream; outputs may not alias inputs. EINVAL for K outside
+ * 1..8, n < 0 or NULL planes with n > 0. */
+int gmm_params_from_raw(int32_t K, int64_t n, const float* logits, const float* log_scales,
+                        float* weights, float* scales, void* stream);
 
 #ifdef __cplusplus
 }

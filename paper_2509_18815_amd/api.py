@@ -27,7 +27,14 @@ class GmmError(RuntimeError):
 class Cfg(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int32), ("lo", ctypes.c_int32), ("hi", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("num_streams", ctypes.c_int32),
-                ("cdf_kind", ctypes.c_int32)]
+                ("cdf_kind", ctypes.c_int32), ("param_kind", ctypes.c_int32)]
+
+
+# cdf_kind values (Sec. III-B and Table II of the paper)
+CDF_AS, CDF_LOGISTIC, CDF_POLYA, CDF_REFERENCE = 0, 1, 2, 3
+# param_kind values: planes hold (weights, means, scales) or raw outputs
+# (weight logits, means, log-scales)
+PARAMS_PLAIN, PARAMS_RAW = 0, 1
 
 
 class DecodeStats(ctypes.Structure):
@@ -66,6 +73,7 @@ _SIGS = {
     "gmm_decode": (ctypes.c_int, [_CFG, _I64, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _I64,
                                   _P, _P]),
     "gmm_fast_recip_mismatches": (ctypes.c_int, [_P, _P]),
+    "gmm_params_from_raw": (ctypes.c_int, [_I32, _I64, _P, _P, _P, _P, _P]),
     "gmm_set_decode_lanes": (ctypes.c_int, [_I32]),
     "gmm_plan_create": (ctypes.c_int, [_CFG, _I32, _P, _P, _I32, _I32, _P]),
     "gmm_plan_exec": (ctypes.c_int, [_P, _P, _P, _P]),
@@ -113,8 +121,9 @@ def status_str(s: int) -> str:
     return lib().gmm_status_str(int(s)).decode()
 
 
-def make_cfg(K, lo, hi, precision=16, streams=256, cdf_kind=0) -> Cfg:
-    return Cfg(int(K), int(lo), int(hi), int(precision), int(streams), int(cdf_kind))
+def make_cfg(K, lo, hi, precision=16, streams=256, cdf_kind=0, param_kind=0) -> Cfg:
+    return Cfg(int(K), int(lo), int(hi), int(precision), int(streams), int(cdf_kind),
+               int(param_kind))
 
 
 def _stream(stream=None) -> int:
@@ -212,12 +221,13 @@ def decode_into(cfg: Cfg, bitstream, offsets, weights, means, scales, symbols, t
                             _opt(status, torch.int32, "status"), _stream(stream))
 
 
-def encode(symbols, weights, means, scales, lo, hi, precision=16, streams=256, cdf_kind=0):
+def encode(symbols, weights, means, scales, lo, hi, precision=16, streams=256, cdf_kind=0,
+           param_kind=0):
     """Encode int32 symbols [n] with [K][n] float32 parameter planes.
     Returns (bitstream int16 tensor of the exact encoded size, offsets int64
     tensor [streams+1]); bitstream words are uint16 values stored as int16."""
     K = weights.shape[0]
-    cfg = make_cfg(K, lo, hi, precision, streams, cdf_kind)
+    cfg = make_cfg(K, lo, hi, precision, streams, cdf_kind, param_kind)
     n = symbols.numel()
     cap = max_words(n, streams)
     bs = torch.empty((max(cap, 1),), dtype=torch.int16, device=symbols.device)
@@ -228,9 +238,9 @@ def encode(symbols, weights, means, scales, lo, hi, precision=16, streams=256, c
 
 
 def decode(bitstream, offsets, weights, means, scales, lo, hi, precision=16, streams=256,
-           cdf_kind=0, bracket=None, stats=None):
+           cdf_kind=0, bracket=None, stats=None, param_kind=0):
     K = weights.shape[0]
-    cfg = make_cfg(K, lo, hi, precision, streams, cdf_kind)
+    cfg = make_cfg(K, lo, hi, precision, streams, cdf_kind, param_kind)
     n = weights.shape[1]
     sym = torch.empty((n,), dtype=torch.int32, device=weights.device)
     bs = bitstream if bitstream.numel() else torch.zeros(1, dtype=torch.int16,
@@ -238,6 +248,21 @@ def decode(bitstream, offsets, weights, means, scales, lo, hi, precision=16, str
     _check(decode_into(cfg, bs, offsets, weights, means, scales, sym,
                        total_words=bitstream.numel(), bracket=bracket, stats=stats), "decode")
     return sym
+
+
+def params_from_raw(logits, log_scales, stream=None):
+    """Raw network outputs [K][n] (weight logits, log-scales; float32 on the
+    device) to (weights, scales) [K][n], by the library's kernel."""
+    assert logits.shape == log_scales.shape and logits.dim() == 2
+    w = torch.empty_like(logits)
+    sg = torch.empty_like(log_scales)
+    _check(lib().gmm_params_from_raw(int(logits.shape[0]), int(logits.shape[1]),
+                                     _dev(logits, torch.float32, "logits"),
+                                     _dev(log_scales, torch.float32, "log_scales"),
+                                     _dev(w, torch.float32, "weights"),
+                                     _dev(sg, torch.float32, "scales"), _stream(stream)),
+           "params_from_raw")
+    return w, sg
 
 
 def set_decode_lanes(lanes: int) -> None:
@@ -259,8 +284,9 @@ class Plan:
     """Batched encode (op=0) or decode (op=1) of B latents with fixed shapes
     (n_b elements, S_b streams each), run as one captured hipGraph."""
 
-    def __init__(self, K, lo, hi, precision, ns, streams, op, autotune=True, cdf_kind=0):
-        self.cfg = make_cfg(K, lo, hi, precision, 1, cdf_kind)
+    def __init__(self, K, lo, hi, precision, ns, streams, op, autotune=True, cdf_kind=0,
+                 param_kind=0):
+        self.cfg = make_cfg(K, lo, hi, precision, 1, cdf_kind, param_kind)
         self.ns = [int(v) for v in ns]
         self.streams = [int(v) for v in streams]
         self.B, self.op = len(self.ns), int(op)

@@ -582,6 +582,7 @@ int gmm_plan_create(const gmm_cfg* common, int32_t B, const int64_t* n_b, const 
   c.num_streams = 1;
   int st = check_cfg(&c, 0);
   if (st) return st;
+  if (c.cdf_kind >= 2) return GMM_EINVAL;  // plans build the A&S and logistic kinds
   for (int b = 0; b < B; ++b)
     if (n_b[b] < 0 || S_b[b] < 1) return GMM_EINVAL;
   gmm_plan* p = new gmm_plan();
@@ -777,7 +778,8 @@ int gmm_plan_set_config(gmm_plan* p, int32_t lanes, int32_t schedule, int32_t wa
 
 int gmm_plan_set_bracket(gmm_plan* p, const gmm_bracket* bracket, gmm_decode_stats* stats) {
   if (!p || p->op != 1) return GMM_EINVAL;
-  if (bracket && (bracket->K != p->cfg.K || p->cfg.K > 5)) return GMM_EINVAL;
+  if (bracket && (bracket->K != p->cfg.K || p->cfg.K > 5 || p->cfg.param_kind != 0))
+    return GMM_EINVAL;
   if (p->cap_stream) (void)hipStreamSynchronize(p->cap_stream);
   (void)hipDeviceSynchronize();
   if (p->gexec) (void)hipGraphExecDestroy(p->gexec);

@@ -226,7 +226,7 @@ __device__ __forceinline__ void bracket_decode_wave(
     }
     if (seg_ok) load_raw<K>(w, mu, sg, n, (p + 1 < ns) ? i + S : s + (ns > 0 ? ns - 1 : 0) * S,
                             nw, nm, nsg);
-    const Elem<K> e = make_elem<K, kFast>(cw, cm, cs);
+    const Elem<K> e = make_elem<K, kFast, kKind>(q, cw, cm, cs);
     const uint32_t slot = x & mask;
     float feat[16];
     lane_features<K>(br, cw, cm, cs, slot, inv_m, feat);

@@ -24,6 +24,7 @@
 #include "../../include/flashgmm.h"
 #include "gmm_device.h"
 #include "gmm_host.h"
+#include "gmm_kernels.h"
 #include "gmm_stream.h"
 
 using namespace fgmm;
@@ -57,57 +58,6 @@ __global__ void k_recip_check(uint32_t lo_bits, uint32_t count, unsigned long lo
   const float a = recip_fast(u);
   const float b = 1.0f / u;
   if (__float_as_uint(a) != __float_as_uint(b)) atomicAdd(mismatches, 1ull);
-}
-
-template <int K, int kKind, bool kFast>
-__global__ void k_cdf_table(QCfg q, int64_t n, const float* __restrict__ w,
-                            const float* __restrict__ mu, const float* __restrict__ sg,
-                            uint32_t* __restrict__ table) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t cols = (int64_t)q.N + 1;
-  if (t >= n * cols) return;
-  const int64_t i = t / cols;
-  const int32_t j = (int32_t)(t - i * cols);
-  float rw[K], rm[K], rs[K];
-  load_raw<K>(w, mu, sg, n, i, rw, rm, rs);
-  const Elem<K> e = make_elem<K, kFast>(rw, rm, rs);
-  table[t] = cdf_at<K, kKind, kFast>(e, q, j);
-}
-
-template <int K, int kKind, bool kFast>
-__global__ void k_inverse(QCfg q, int rounds, int64_t n, const float* __restrict__ w,
-                          const float* __restrict__ mu, const float* __restrict__ sg,
-                          const uint32_t* __restrict__ slot, int32_t* __restrict__ jout,
-                          uint32_t* status) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  float rw[K], rm[K], rs[K];
-  load_raw<K>(w, mu, sg, n, i, rw, rm, rs);
-  const Elem<K> e = make_elem<K, kFast>(rw, rm, rs);
-  uint32_t s = slot[i];
-  if (s >= q.M) {
-    atomicOr(status, kStInval);
-    s = q.M - 1;
-  }
-  uint32_t cl, ch;
-  jout[i] = search_bs<K, kKind, kFast>(e, q, rounds, s, cl, ch);
-}
-
-// Encode phase 1: one thread per element (per pass position with kGather:
-// element idx[i] of a latent of n_total elements).
-template <int K, int kKind, bool kFast, bool kGather = false>
-__global__ void k_enc_cdf(QCfg q, int64_t n, const int32_t* __restrict__ sym,
-                          const float* __restrict__ w, const float* __restrict__ mu,
-                          const float* __restrict__ sg, uint32_t* __restrict__ cf,
-                          uint32_t* status, const int32_t* __restrict__ idx = nullptr,
-                          int64_t n_total = 0) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  if (kGather)
-    cf[i] = enc_cdf_elem<K, kKind, kFast>(q, n_total, gather_index(idx, i, n_total), sym, w, mu,
-                                           sg, status);
-  else
-    cf[i] = enc_cdf_elem<K, kKind, kFast>(q, n, i, sym, w, mu, sg, status);
 }
 
 constexpr int kRansBlock = 256;
@@ -162,23 +112,27 @@ __global__ void __launch_bounds__(kPackBlock)
                kPackLanes);
 }
 
-// Decode with L lanes per stream (L = 1: one lane per stream and a binary
-// search; L > 1: an (L+1)-ary search, ceil(log_{L+1} N) rounds).
-template <int K, int kKind, bool kFast, int L, bool kGather = false>
-__global__ void __launch_bounds__(256)
-    k_decode(QCfg q, int P, int rounds, int64_t n, int64_t S, const uint16_t* __restrict__ bs,
-             int64_t total_words, const int64_t* __restrict__ offsets,
-             const float* __restrict__ w, const float* __restrict__ mu,
-             const float* __restrict__ sg, int32_t* __restrict__ sym, uint32_t* status,
-             const int32_t* __restrict__ idx = nullptr, int64_t n_total = 0) {
-  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t s = gt / L;
-  const int g = (int)(gt % L);
-  // groups never straddle the S boundary (S * L lanes, L divides 64)
-  if (s >= S) return;
-  const bool bad = decode_stream<K, kKind, kFast, L, kGather>(
-      q, P, rounds, n, S, s, g, bs, total_words, offsets, w, mu, sg, sym, idx, n_total);
-  if (bad && g == 0) atomicOr(status, kStCorrupt);
+// Raw network outputs to mixture parameters as a pass of its own (the
+// coder kernels apply the same mapping per element when param_kind = 1):
+// weights [K][n] from logits, scales [K][n] from log-scales.
+template <int K>
+__global__ void k_params_from_raw(int64_t n, const float* __restrict__ logits,
+                                  const float* __restrict__ log_scales, float* __restrict__ w,
+                                  float* __restrict__ sg) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float a[K], b[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    a[k] = logits[k * n + i];
+    b[k] = log_scales[k * n + i];
+  }
+  fgmm::raw_to_params<K>(a, b);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    w[k * n + i] = a[k];
+    sg[k * n + i] = b[k];
+  }
 }
 
 // Subset (gather) pass of a latent: validates idx (every entry in
@@ -226,7 +180,8 @@ int check_cfg(const gmm_cfg* c, int64_t n) {
   if (c->K < 1 || c->K > kMaxK) return GMM_EINVAL;
   if (c->precision < 2 || c->precision > 16) return GMM_EINVAL;
   if (c->num_streams < 1) return GMM_EINVAL;
-  if (c->cdf_kind != 0 && c->cdf_kind != 1) return GMM_EINVAL;
+  if (c->cdf_kind < 0 || c->cdf_kind > 3) return GMM_EINVAL;
+  if (c->param_kind != 0 && c->param_kind != 1) return GMM_EINVAL;
   if (c->lo < -(1 << 22) || c->hi > (1 << 22) || c->hi <= c->lo) return GMM_EINVAL;
   const int64_t N = (int64_t)c->hi - c->lo + 1;
   const int64_t M = (int64_t)1 << c->precision;
@@ -240,6 +195,7 @@ QCfg make_qcfg(const gmm_cfg* c) {
   q.N = c->hi - c->lo + 1;
   q.M = 1u << c->precision;
   q.span = (float)(q.M - (uint32_t)q.N);
+  q.raw = c->param_kind;
   return q;
 }
 
@@ -318,6 +274,9 @@ int encode_launch(const gmm_cfg* cfg, int64_t n, const int32_t* symbols, const f
   if (n > 0) {
     const dim3 grid((unsigned)((n + 255) / 256)), block(256);
     if (idx) hipLaunchKernelGGL(k_check_idx, grid, block, 0, st, idx, n, n_total, status);
+    if (cfg->cdf_kind >= 2)
+      ablation_enc_cdf(q, cfg->K, cfg->cdf_kind, n, symbols, w, mu, sg, cf, status, st);
+    else
     dispatch(cfg->K, cfg->cdf_kind, fast, [&](auto Kc, auto kc, auto fc) {
       constexpr int K_ = decltype(Kc)::value, KI = decltype(kc)::value;
       constexpr bool F = decltype(fc)::value;
@@ -364,7 +323,8 @@ int decode_launch(const gmm_cfg* cfg, int64_t n, const uint16_t* bs, int64_t tot
                   const int32_t* idx, int64_t n_total) {
   const int64_t S = cfg->num_streams;
   const QCfg q = make_qcfg(cfg);
-  const int L = (lanes > 0) ? lanes : default_lanes_per_stream(S);
+  int L = (lanes > 0) ? lanes : default_lanes_per_stream(S);
+  if (cfg->cdf_kind >= 2) L = (L == 1) ? 1 : 16;  // the comparison kinds build L = 1 and 16
   const int rounds = (L == 1) ? search_rounds(q.N) : search_rounds_lps(q.N, L);
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, status, 0u, (int64_t)1);
   if (idx && n > 0)
@@ -373,6 +333,12 @@ int decode_launch(const gmm_cfg* cfg, int64_t n, const uint16_t* bs, int64_t tot
   const int64_t threads = S * L;
   const int blk = (L == 1) ? 64 : 256;
   const dim3 grid((unsigned)((threads + blk - 1) / blk)), block(blk);
+  if (cfg->cdf_kind >= 2) {
+    if (idx) return GMM_EINVAL;
+    ablation_decode(q, cfg->K, cfg->cdf_kind, cfg->precision, rounds, L, n, S, bs, total_words,
+                    offsets, w, mu, sg, symbols, status, st);
+    return hipGetLastError() == hipSuccess ? GMM_OK : GMM_EDEVICE;
+  }
   dispatch(cfg->K, cfg->cdf_kind, fast, [&](auto Kc, auto kc, auto fc) {
     constexpr int K_ = decltype(Kc)::value, KI = decltype(kc)::value;
     constexpr bool F = decltype(fc)::value;
@@ -455,6 +421,9 @@ int gmm_cdf_table(const gmm_cfg* cfg, int64_t n, const float* w, const float* mu
   const fgmm::QCfg q = fgmm::make_qcfg(cfg);
   const int64_t total = n * ((int64_t)q.N + 1);
   if (total == 0) return GMM_OK;
+  if (cfg->cdf_kind >= 2)
+    fgmm::ablation_cdf_table(q, cfg->K, cfg->cdf_kind, n, w, mu, sg, table, st);
+  else
   fgmm::dispatch(cfg->K, cfg->cdf_kind, fast, [&](auto Kc, auto kc, auto fc) {
     hipLaunchKernelGGL((k_cdf_table<decltype(Kc)::value, decltype(kc)::value,
                                     decltype(fc)::value>),
@@ -477,7 +446,9 @@ int gmm_inverse_cdf(const gmm_cfg* cfg, int64_t n, const float* w, const float* 
   uint32_t* status = nullptr;
   if (hipMallocAsync((void**)&status, 256, st) != hipSuccess) return GMM_ENOMEM;
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, status, 0u, (int64_t)1);
-  if (n > 0) {
+  if (n > 0 && cfg->cdf_kind >= 2) {
+    fgmm::ablation_inverse(q, cfg->K, cfg->cdf_kind, rounds, n, w, mu, sg, slot, jout, status, st);
+  } else if (n > 0) {
     fgmm::dispatch(cfg->K, cfg->cdf_kind, fast, [&](auto Kc, auto kc, auto fc) {
       hipLaunchKernelGGL((k_inverse<decltype(Kc)::value, decltype(kc)::value,
                                     decltype(fc)::value>),
@@ -535,6 +506,10 @@ int gmm_decode(const gmm_cfg* cfg, int64_t n, const uint16_t* bitstream, int64_t
   } else if (ws_bytes < 256) {
     return GMM_EINVAL;
   }
+  if (bracket && (cfg->cdf_kind >= 2 || cfg->param_kind != 0)) {
+    if (own) (void)hipFreeAsync(wsp, st);
+    return GMM_EINVAL;
+  }
   const bool fast = fgmm::use_fast_recip(st);
   int r;
   if (bracket) {
@@ -555,6 +530,7 @@ int gmm_encode_subset(const gmm_cfg* cfg, int64_t n_total, const int32_t* idx, i
                       int64_t ws_bytes, int32_t* dev_status, void* stream) {
   int st0 = fgmm::check_cfg(cfg, m);
   if (st0) return st0;
+  if (cfg->cdf_kind >= 2) return GMM_EINVAL;  // subset passes build the plain kinds only
   if (n_total < 0 || m > n_total || (m > 0 && (!idx || n_total > INT32_MAX))) return GMM_EINVAL;
   if (!offsets || capacity_words < 0) return GMM_EINVAL;
   if (m > 0 && (!symbols || !w || !mu || !sg)) return GMM_EINVAL;
@@ -583,6 +559,7 @@ int gmm_decode_subset(const gmm_cfg* cfg, int64_t n_total, const int32_t* idx, i
                       void* ws, int64_t ws_bytes, int32_t* dev_status, void* stream) {
   int st0 = fgmm::check_cfg(cfg, m);
   if (st0) return st0;
+  if (cfg->cdf_kind >= 2) return GMM_EINVAL;  // subset passes build the plain kinds only
   if (n_total < 0 || m > n_total || (m > 0 && (!idx || n_total > INT32_MAX))) return GMM_EINVAL;
   if (!offsets || total_words < 0) return GMM_EINVAL;
   if (m > 0 && (!symbols || !w || !mu || !sg)) return GMM_EINVAL;
@@ -602,6 +579,22 @@ int gmm_decode_subset(const gmm_cfg* cfg, int64_t n_total, const int32_t* idx, i
   if (r == GMM_OK) r = fgmm::finish((uint32_t*)wsp, dev_status, st);
   if (own) (void)hipFreeAsync(wsp, st);
   return r;
+}
+
+int gmm_params_from_raw(int32_t K, int64_t n, const float* logits, const float* log_scales,
+                        float* weights, float* scales, void* stream) {
+  if (K < 1 || K > fgmm::kMaxK || n < 0) return GMM_EINVAL;
+  if (n > 0 && (!logits || !log_scales || !weights || !scales)) return GMM_EINVAL;
+  if (n == 0) return GMM_OK;
+  hipStream_t st = (hipStream_t)stream;
+  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  switch (K) {
+#define FG_RAW(KK) \
+  case KK: hipLaunchKernelGGL(k_params_from_raw<KK>, grid, block, 0, st, n, logits, log_scales, weights, scales); break;
+    FG_RAW(1) FG_RAW(2) FG_RAW(3) FG_RAW(4) FG_RAW(5) FG_RAW(6) FG_RAW(7) FG_RAW(8)
+#undef FG_RAW
+  }
+  return hipGetLastError() == hipSuccess ? GMM_OK : GMM_EDEVICE;
 }
 
 int gmm_fast_recip_mismatches(uint64_t* count, void* stream) {

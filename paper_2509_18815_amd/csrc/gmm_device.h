@@ -4,7 +4,9 @@
 // the mixture CDF difference across the half-integer boundaries y-1/2 and
 // y+1/2 (FlashGMM paper, Eq. (1) with the mixture of Eq. (2)); FlashGMM
 // evaluates that CDF only at the boundaries rANS needs (Sec. III-A), with a
-// closed-form Gaussian CDF approximation (Sec. III-B).
+// closed-form Gaussian CDF approximation (Sec. III-B: A&S 26.2.17, the
+// logistic function, Polya's formula), or, as Table II's unapproximated
+// baseline, a binary64 evaluation from series and continued fraction.
 //
 // Binary32 contract (bit-exact between encoder and decoder, and with any
 // conforming implementation): explicit fused multiply-adds only (the library
@@ -37,6 +39,22 @@ constexpr float kF6 = 0x1.6c16c2p-10f;
 constexpr float kF5 = 0x1.111112p-7f;
 constexpr float kF4 = 0x1.555556p-5f;
 constexpr float kF3 = 0x1.555556p-3f;
+constexpr float kF8 = 0x1.a01a02p-16f;  // 1/8!
+// Polya: Phi(x) ~ (1 + sign(x) sqrt(1 - exp(-(2/pi) x^2))) / 2
+constexpr float kPolyaC = 0x1.45f306p-1f;  // 2/pi
+// lower bound of scales mapped from raw log-scale outputs
+constexpr float kScaleMin = 0x1.c28f5cp-4f;  // 0.11
+
+// binary64 reference CDF: exp with ln 2 split so that n * kLn2HiD is exact
+// for |n| < 2^11; Taylor coefficients 1/k!, k = 0..13.
+constexpr double kLog2eD = 0x1.71547652b82fep+0;
+constexpr double kLn2HiD = 0x1.62e42fefa38p-1;
+constexpr double kLn2LoD = 0x1.ef35793c7673p-45;
+constexpr double kInvSqrt2D = 0x1.6a09e667f3bcdp-1;
+constexpr double kInvSqrtPiD = 0x1.20dd750429b6dp-1;
+constexpr double kHalfInvSqrtPiD = 0x1.20dd750429b6dp-2;
+constexpr int kErfTerms = 32;     // Maclaurin terms of erf, x < 2
+constexpr int kErfcCfDepth = 50;  // continued-fraction levels of erfc, x >= 2
 
 constexpr int kMaxK = 8;
 
@@ -44,7 +62,7 @@ __device__ __forceinline__ float fma32(float a, float b, float c) {
   return __builtin_fmaf(a, b, c);
 }
 
-// exp(g) for g in [-40.5, 0]: n = rint(g log2 e), r = g - n ln 2 in two
+// exp(g) for g in [-51.6, 7]: n = rint(g log2 e), r = g - n ln 2 in two
 // fused steps, degree-7 Taylor polynomial of e^r by Horner, times 2^n
 // (the result is always a normal float).
 __device__ __forceinline__ float exp_tilde(float g) {
@@ -99,21 +117,141 @@ __device__ __forceinline__ float tail_logistic(float a) {
   return e / (1.0f + e);
 }
 
-// Phi~(z): z clamped to [-9, 9]; Phi(-a) = tail(a), Phi(a) = 1 - tail(a);
-// the tail is capped at 1/2 (the float A&S tail exceeds 1/2 by one ulp for
-// tiny a), which keeps Phi~ non-decreasing across z = 0.
+// Upper tail of Polya's approximation, (1 - sqrt(E)) / 2 with
+// E = 1 - exp(-u), u = (2/pi) a^2, in the form (e/2) / (1 + sqrt(E)) that
+// does not cancel for large a; E comes from the Taylor series of -expm1
+// for u < 1/4 (where 1 - e would cancel) and from 1 - e above. Both
+// candidates are computed and one is selected, so lanes do not diverge.
+__device__ __forceinline__ float tail_polya(float a) {
+  const float m = a * a;
+  const float u = m * kPolyaC;
+  const float g = -u;
+  const float e = exp_tilde(g);
+  float p = kF8;
+  p = fma32(p, g, kF7);
+  p = fma32(p, g, kF6);
+  p = fma32(p, g, kF5);
+  p = fma32(p, g, kF4);
+  p = fma32(p, g, kF3);
+  p = fma32(p, g, 0.5f);
+  p = fma32(p, g, 1.0f);
+  const float E = (u < 0.25f) ? u * p : 1.0f - e;
+  const float s = __builtin_sqrtf(E);
+  const float h = e * 0.5f;
+  return h / (1.0f + s);
+}
+
+// Phi~(z) for the binary32 kinds (0 A&S, 1 logistic, 2 Polya): z clamped
+// to [-9, 9]; Phi(-a) = tail(a), Phi(a) = 1 - tail(a); the tail is capped at
+// 1/2 (the float A&S tail exceeds 1/2 by one ulp for tiny a), which keeps
+// Phi~ non-decreasing across z = 0.
 template <int kKind, bool kFastRecip>
 __device__ __forceinline__ float phi_tilde(float z) {
   z = __builtin_fminf(__builtin_fmaxf(z, -9.0f), 9.0f);
   const float a = __builtin_fabsf(z);
-  float tail = (kKind == 1) ? tail_logistic(a) : tail_as<kFastRecip>(a);
+  float tail = (kKind == 1)   ? tail_logistic(a)
+               : (kKind == 2) ? tail_polya(a)
+                              : tail_as<kFastRecip>(a);
   tail = __builtin_fminf(tail, 0.5f);
   return (z < 0.0f) ? tail : 1.0f - tail;
 }
 
+// exp(g) in binary64 for g in [-686, 0]: Cody & Waite reduction, Taylor
+// polynomial of degree 13 (|r| <= 0.35), times 2^n (normal result).
+__device__ __forceinline__ double exp_d(double g) {
+  constexpr double kInvFact[14] = {1.0,
+                                   1.0,
+                                   0x1p-1,
+                                   0x1.5555555555555p-3,
+                                   0x1.5555555555555p-5,
+                                   0x1.1111111111111p-7,
+                                   0x1.6c16c16c16c17p-10,
+                                   0x1.a01a01a01a01ap-13,
+                                   0x1.a01a01a01a01ap-16,
+                                   0x1.71de3a556c734p-19,
+                                   0x1.27e4fb7789f5cp-22,
+                                   0x1.ae64567f544e4p-26,
+                                   0x1.1eed8eff8d898p-29,
+                                   0x1.6124613a86d09p-33};
+  const double n = __builtin_rint(g * kLog2eD);
+  double r = __builtin_fma(-n, kLn2HiD, g);
+  r = __builtin_fma(-n, kLn2LoD, r);
+  double p = kInvFact[13];
+#pragma unroll
+  for (int k = 12; k >= 0; --k) p = __builtin_fma(p, r, kInvFact[k]);
+  return __builtin_ldexp(p, (int)n);
+}
+
+// Gaussian upper tail Q(a) = erfc(a / sqrt 2) / 2 in binary64, a in [0, 37].
+// With x = a / sqrt 2, y = x^2: for x < 2 the Maclaurin series of erf,
+// nested as s_{n-1} = 1/(2n-1) - (y/n) s_n from s_N = 1/(2N+1), gives
+// Q = 1/2 - x s / sqrt(pi); for x >= 2 Laplace's continued fraction
+// erfc(x) = exp(-y) / sqrt(pi) / (x + (1/2)/(x + 1/(x + (3/2)/(x + ...)))),
+// evaluated bottom-up from a fixed depth, gives Q = exp(-y)/(2 sqrt pi)/u.
+__device__ __forceinline__ double tail_ref(double a) {
+  const double x = a * kInvSqrt2D;
+  const double y = x * x;
+  if (x < 2.0) {
+    double s = 1.0 / (2 * kErfTerms + 1);
+#pragma unroll
+    for (int n = kErfTerms; n >= 1; --n) {
+      const double v = y * (1.0 / n);
+      s = __builtin_fma(-v, s, 1.0 / (2 * n - 1));
+    }
+    const double t1 = x * s;
+    return __builtin_fma(-kInvSqrtPiD, t1, 0.5);
+  }
+  double u = x;
+  for (int m = kErfcCfDepth; m >= 1; --m) u = x + (0.5 * m) / u;
+  const double e = exp_d(-y);
+  const double t2 = e * kHalfInvSqrtPiD;
+  return t2 / u;
+}
+
+// Reference Phi(z) in binary64: z clamped to [-37, 37] (exp stays normal).
+__device__ __forceinline__ double phi_ref(double z) {
+  z = __builtin_fmin(__builtin_fmax(z, -37.0), 37.0);
+  const double q = tail_ref(__builtin_fabs(z));
+  return (z < 0.0) ? q : 1.0 - q;
+}
+
+// Quantization constants of one configuration.
+struct QCfg {
+  int32_t lo;      // smallest symbol
+  int32_t N;       // alphabet size
+  uint32_t M;      // 2^P
+  float span;      // (float)(M - N)
+  int32_t raw;     // 1: parameter planes hold raw outputs (weight logits, log-scales)
+};
+
+// Raw outputs of one element to weights and scales, in place: softmax of
+// the logits (differences to the largest, in component order, floored at
+// -40.5; the sum in component order; IEEE division) and
+// sigma = max(exp~(clamp(t, -7, 7)), 0.11) of the log-scales t.
+template <int K>
+__device__ __forceinline__ void raw_to_params(float (&w)[K], float (&s)[K]) {
+  float m = w[0];
+#pragma unroll
+  for (int k = 1; k < K; ++k) m = __builtin_fmaxf(m, w[k]);
+  float e[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) e[k] = exp_tilde(__builtin_fmaxf(w[k] - m, -40.5f));
+  float sum = e[0];
+#pragma unroll
+  for (int k = 1; k < K; ++k) sum = sum + e[k];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    w[k] = e[k] / sum;
+    s[k] = __builtin_fmaxf(exp_tilde(__builtin_fminf(__builtin_fmaxf(s[k], -7.0f), 7.0f)),
+                           kScaleMin);
+  }
+}
+
 // One element's parameters after the per-element clamps: scale clamped to
-// [2^-10, 2^10] then reciprocated (IEEE division); weights below 2^-60
-// (including negative ones) become 0. Parameter planes are [K][n].
+// [2^-10, 2^10] then reciprocated (IEEE division; the binary64 reference
+// kind keeps the clamped scale itself and divides in binary64); weights
+// below 2^-60 (including negative ones) become 0. With q.raw the planes
+// hold raw outputs, mapped first. Parameter planes are [K][n].
 template <int K>
 struct Elem {
   float w[K], mu[K], r[K];
@@ -131,33 +269,44 @@ __device__ __forceinline__ void load_raw(const float* __restrict__ w, const floa
   }
 }
 
-template <int K, bool kFastRecip>
-__device__ __forceinline__ Elem<K> make_elem(const float (&rw)[K], const float (&rm)[K],
-                                             const float (&rs)[K]) {
+template <int K, bool kFastRecip, int kKind = 0>
+__device__ __forceinline__ Elem<K> make_elem(const QCfg& q, const float (&rw)[K],
+                                             const float (&rm)[K], const float (&rs)[K]) {
+  float w[K], sc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    w[k] = rw[k];
+    sc[k] = rs[k];
+  }
+  if (q.raw) raw_to_params<K>(w, sc);
   Elem<K> e;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const float s = __builtin_fminf(__builtin_fmaxf(rs[k], 0x1p-10f), 0x1p10f);
-    e.r[k] = kFastRecip ? recip_fast(s) : 1.0f / s;
-    e.w[k] = (rw[k] < 0x1p-60f) ? 0.0f : rw[k];
+    const float s = __builtin_fminf(__builtin_fmaxf(sc[k], 0x1p-10f), 0x1p10f);
+    e.r[k] = (kKind == 3) ? s : (kFastRecip ? recip_fast(s) : 1.0f / s);
+    e.w[k] = (w[k] < 0x1p-60f) ? 0.0f : w[k];
     e.mu[k] = rm[k];
   }
   return e;
 }
-
-// Quantization constants of one configuration.
-struct QCfg {
-  int32_t lo;      // smallest symbol
-  int32_t N;       // alphabet size
-  uint32_t M;      // 2^P
-  float span;      // (float)(M - N)
-};
 
 // Quantized CDF c_j at boundary b_j = lo + j - 1/2 for j in [1, N-1]:
 // F = sum_k w_k Phi~((b - mu_k) r_k) accumulated in component order with
 // fused multiply-adds, clamped to 1; c_j = j + floor(F (M - N)).
 template <int K, int kKind, bool kFastRecip>
 __device__ __forceinline__ uint32_t cdf_inner(const Elem<K>& e, const QCfg& q, int32_t j) {
+  if constexpr (kKind == 3) {
+    // binary64 reference: z = (b - mu) / sigma, F and its quantization in binary64
+    const double b = (double)(q.lo + j) - 0.5;
+    double F = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const double z = (b - (double)e.mu[k]) / (double)e.r[k];
+      F = __builtin_fma((double)e.w[k], phi_ref(z), F);
+    }
+    F = __builtin_fmin(F, 1.0);
+    return (uint32_t)j + (uint32_t)__builtin_floor(F * (double)(q.M - (uint32_t)q.N));
+  }
   const float b = (float)(q.lo + j) - 0.5f;
   float F = 0.0f;
 #pragma unroll

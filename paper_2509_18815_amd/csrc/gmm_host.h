@@ -31,6 +31,21 @@ int decode_bracket_launch(const gmm_cfg* cfg, int64_t n, const uint16_t* bs, int
                           const float* sg, int32_t* symbols, const gmm_bracket* bracket,
                           gmm_decode_stats* stats, uint32_t* status, bool fast, hipStream_t st);
 
+// Launchers of the Polya (kind 2) and binary64-reference (kind 3) CDF
+// kernels (gmm_ablation.hip); launch errors are left for hipGetLastError.
+void ablation_cdf_table(const QCfg& q, int K, int kind, int64_t n, const float* w,
+                        const float* mu, const float* sg, uint32_t* table, hipStream_t st);
+void ablation_inverse(const QCfg& q, int K, int kind, int rounds, int64_t n, const float* w,
+                      const float* mu, const float* sg, const uint32_t* slot, int32_t* jout,
+                      uint32_t* status, hipStream_t st);
+void ablation_enc_cdf(const QCfg& q, int K, int kind, int64_t n, const int32_t* sym,
+                      const float* w, const float* mu, const float* sg, uint32_t* cf,
+                      uint32_t* status, hipStream_t st);
+void ablation_decode(const QCfg& q, int K, int kind, int P, int rounds, int L, int64_t n,
+                     int64_t S, const uint16_t* bs, int64_t total_words, const int64_t* offsets,
+                     const float* w, const float* mu, const float* sg, int32_t* sym,
+                     uint32_t* status, hipStream_t st);
+
 // Calls fn(integral_constant<K>, integral_constant<kind>, bool_constant<fast>)
 // for the runtime (K, kind, fast) (the logistic kind has no division to
 // replace, so its fast flag is always false).

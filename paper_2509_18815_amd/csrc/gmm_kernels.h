@@ -1,0 +1,87 @@
+// Templated coder kernels shared by the translation units that instantiate
+// them: the plain path for the A&S and logistic CDFs (gmm_coder.hip) and the
+// Polya / binary64-reference kinds of the Table II comparison
+// (gmm_ablation.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gmm_device.h"
+#include "gmm_stream.h"
+
+// (global namespace, so that profiles name the kernels briefly)
+
+template <int K, int kKind, bool kFast>
+__global__ void k_cdf_table(fgmm::QCfg q, int64_t n, const float* __restrict__ w,
+                            const float* __restrict__ mu, const float* __restrict__ sg,
+                            uint32_t* __restrict__ table) {
+  using namespace fgmm;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t cols = (int64_t)q.N + 1;
+  if (t >= n * cols) return;
+  const int64_t i = t / cols;
+  const int32_t j = (int32_t)(t - i * cols);
+  float rw[K], rm[K], rs[K];
+  load_raw<K>(w, mu, sg, n, i, rw, rm, rs);
+  const Elem<K> e = make_elem<K, kFast, kKind>(q, rw, rm, rs);
+  table[t] = cdf_at<K, kKind, kFast>(e, q, j);
+}
+
+template <int K, int kKind, bool kFast>
+__global__ void k_inverse(fgmm::QCfg q, int rounds, int64_t n, const float* __restrict__ w,
+                          const float* __restrict__ mu, const float* __restrict__ sg,
+                          const uint32_t* __restrict__ slot, int32_t* __restrict__ jout,
+                          uint32_t* status) {
+  using namespace fgmm;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float rw[K], rm[K], rs[K];
+  load_raw<K>(w, mu, sg, n, i, rw, rm, rs);
+  const Elem<K> e = make_elem<K, kFast, kKind>(q, rw, rm, rs);
+  uint32_t s = slot[i];
+  if (s >= q.M) {
+    atomicOr(status, kStInval);
+    s = q.M - 1;
+  }
+  uint32_t cl, ch;
+  jout[i] = search_bs<K, kKind, kFast>(e, q, rounds, s, cl, ch);
+}
+
+// Encode phase 1: one thread per element (per pass position with kGather:
+// element idx[i] of a latent of n_total elements).
+template <int K, int kKind, bool kFast, bool kGather = false>
+__global__ void k_enc_cdf(fgmm::QCfg q, int64_t n, const int32_t* __restrict__ sym,
+                          const float* __restrict__ w, const float* __restrict__ mu,
+                          const float* __restrict__ sg, uint32_t* __restrict__ cf,
+                          uint32_t* status, const int32_t* __restrict__ idx = nullptr,
+                          int64_t n_total = 0) {
+  using namespace fgmm;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (kGather)
+    cf[i] = enc_cdf_elem<K, kKind, kFast>(q, n_total, gather_index(idx, i, n_total), sym, w, mu,
+                                           sg, status);
+  else
+    cf[i] = enc_cdf_elem<K, kKind, kFast>(q, n, i, sym, w, mu, sg, status);
+}
+
+// Decode with L lanes per stream (L = 1: one lane per stream and a binary
+// search; L > 1: an (L+1)-ary search, ceil(log_{L+1} N) rounds).
+template <int K, int kKind, bool kFast, int L, bool kGather = false>
+__global__ void __launch_bounds__(256)
+    k_decode(fgmm::QCfg q, int P, int rounds, int64_t n, int64_t S, const uint16_t* __restrict__ bs,
+             int64_t total_words, const int64_t* __restrict__ offsets,
+             const float* __restrict__ w, const float* __restrict__ mu,
+             const float* __restrict__ sg, int32_t* __restrict__ sym, uint32_t* status,
+             const int32_t* __restrict__ idx = nullptr, int64_t n_total = 0) {
+  using namespace fgmm;
+  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t s = gt / L;
+  const int g = (int)(gt % L);
+  // groups never straddle the S boundary (S * L lanes, L divides 64)
+  if (s >= S) return;
+  const bool bad = decode_stream<K, kKind, kFast, L, kGather>(
+      q, P, rounds, n, S, s, g, bs, total_words, offsets, w, mu, sg, sym, idx, n_total);
+  if (bad && g == 0) atomicOr(status, kStCorrupt);
+}
+

@@ -97,7 +97,7 @@ __device__ __forceinline__ uint32_t enc_cdf_elem(const QCfg& q, int64_t n, int64
     atomicOr(status, kStRange);
     j = 0;
   }
-  const Elem<K> e = make_elem<K, kFast>(rw, rm, rs);
+  const Elem<K> e = make_elem<K, kFast, kKind>(q, rw, rm, rs);
   const uint32_t c0 = cdf_at<K, kKind, kFast>(e, q, j);
   const uint32_t c1 = cdf_at<K, kKind, kFast>(e, q, j + 1);
   return (c0 << 16) | (c1 - c0);
@@ -305,7 +305,7 @@ __device__ __forceinline__ bool decode_stream(const QCfg& q, int P, int rounds, 
           cm[k] = opaque_copy(rm[d][k]);
           cs[k] = opaque_copy(rs[d][k]);
         }
-        const Elem<K> e = make_elem<K, kFast>(cw, cm, cs);
+        const Elem<K> e = make_elem<K, kFast, kKind>(q, cw, cm, cs);
         int32_t j;
         if (L == 1)
           j = search_bs<K, kKind, kFast>(e, q, rounds, slot, cl, ch);

@@ -189,6 +189,20 @@ def random_params(rng, n, K, s_logit=1.0, s_mu=2.0, sigma_max=20.0, sigma_min=0.
     return (np.ascontiguousarray(w.T), np.ascontiguousarray(mu.T), np.ascontiguousarray(sig.T))
 
 
+def raw_params(rng, n, K, s_logit=1.0, s_mu=2.0, sigma_max=20.0, sigma_min=0.11):
+    """A network's raw outputs for the same distributions as random_params:
+    weight logits ~ N(0, s_logit), means ~ N(0, s_mu), log-scales
+    ~ U(ln sigma_min, ln sigma_max); [K][n] float32 planes. A few elements
+    get extreme logits and log-scales (the mapping's clamps)."""
+    logits = rng.normal(0.0, s_logit, size=(K, n)).astype(np.float32)
+    mu = rng.normal(0.0, s_mu, size=(K, n)).astype(np.float32)
+    log_s = rng.uniform(math.log(sigma_min), math.log(sigma_max), size=(K, n)).astype(np.float32)
+    m = min(n, 64)
+    logits[:, :m] = rng.uniform(-90.0, 90.0, size=(K, m)).astype(np.float32)
+    log_s[:, :m] = rng.uniform(-12.0, 12.0, size=(K, m)).astype(np.float32)
+    return logits, mu, log_s
+
+
 def adversarial_params(rng, n, K):
     """Parameters at the edges of the numeric range: tiny and huge scales,
     zero and denormal-range weights, means far outside the support, ties."""
