@@ -46,11 +46,12 @@ def encode_flops_per_symbol(K: int) -> int:
 
 
 class Latent:
-    def __init__(self, api, cfgd, lat):
+    def __init__(self, api, cfgd, lat, cdf_kind=0, param_kind=0):
         import torch
         self.api, self.cfgd, self.lat = api, cfgd, lat
         self.n, self.S = lat.n, lat.streams
-        self.cfg = api.make_cfg(cfgd.K, cfgd.lo, cfgd.hi, cfgd.precision, self.S)
+        self.cfg = api.make_cfg(cfgd.K, cfgd.lo, cfgd.hi, cfgd.precision, self.S, cdf_kind,
+                                param_kind)
         dev = lat.symbols.device
         self.bs = torch.empty(api.max_words(self.n, self.S), dtype=torch.int16, device=dev)
         self.off = torch.empty(self.S + 1, dtype=torch.int64, device=dev)
@@ -349,6 +350,101 @@ def bracket_single_form(api, synth, dev, model, reps=5):
             "training": model.history[-2:]}
 
 
+# The paper's Table II (CPU, per 768x512 Kodak image; encode / decode ms),
+# quoted as context for the same comparison on one MI355X.
+PAPER_TABLE2_MS = {"no_approximation": (56.5, 127.0), "polya": (23.5, 34.3),
+                   "as_26_2_17": (22.5, 33.7), "logistic": (22.5, 33.2)}
+
+
+def table2_form(api, synth, dev, reps=5):
+    """Speed of the Gaussian-CDF kinds of the paper's Table II on the
+    320x48x32 latent (4,096 streams): encode and decode time per latent for
+    the binary64 reference (standing in for the unapproximated erfc), Polya,
+    A&S 26.2.17 and logistic, each round trip verified."""
+    import torch
+    cfgd = synth.CONFIGS["c2a"]
+    lat = synth.make_latents(cfgd, backend="torch", device=dev)[0]
+    stream = torch.cuda.current_stream()
+    out = {"latent": list(lat.shape), "n": lat.n, "streams": lat.streams}
+    for kind, name in ((3, "no_approximation"), (2, "polya"), (0, "as_26_2_17"),
+                       (1, "logistic")):
+        L = Latent(api, cfgd, lat, cdf_kind=kind)
+        L.encode()
+        L.decode()
+        torch.cuda.synchronize()
+        L.verify()
+        t_e = time_events(L.encode, reps, stream)
+        t_d = time_events(L.decode, reps, stream)
+        torch.cuda.synchronize()
+        L.verify()
+        out[name] = {"encode_ms": round(t_e * 1e3, 4), "decode_ms": round(t_d * 1e3, 4),
+                     "encode_sym_s": L.n / t_e, "decode_sym_s": L.n / t_d,
+                     "bits_per_symbol": 16.0 * float(L.off[-1].item()) / L.n,
+                     "paper_cpu_ms": PAPER_TABLE2_MS[name]}
+    return out
+
+
+def epilogue_form(api, synth, dev, reps=5):
+    """Coding from a network's raw outputs on the 4K latent (320x135x240,
+    65,536 streams): the mapping (softmax of weight logits, exp of
+    log-scales) fused into the coder kernels, against a separate mapping
+    pass (gmm_params_from_raw) before each plain encode and decode. The raw
+    outputs are log-weights and log-scales of the plain workload, so the
+    symbols and the model match the plain 4K measurement."""
+    import torch
+    cfgd = synth.CONFIGS["c2b"]
+    lat = synth.make_latents(cfgd, backend="torch", device=dev)[0]
+    logits = torch.log(lat.weights).contiguous()
+    log_s = torch.log(lat.scales).contiguous()
+    raw = synth.Latent(lat.symbols, logits, lat.means, log_s, lat.shape, lat.streams)
+    Lr = Latent(api, cfgd, raw, param_kind=1)
+    w_m = torch.empty_like(logits)
+    s_m = torch.empty_like(log_s)
+    mapped = synth.Latent(lat.symbols, w_m, lat.means, s_m, lat.shape, lat.streams)
+    Lp = Latent(api, cfgd, mapped)
+    stream = torch.cuda.current_stream()
+
+    def mapping():
+        r = api.lib().gmm_params_from_raw(cfgd.K, lat.n, api._dev(logits, torch.float32, "l"),
+                                          api._dev(log_s, torch.float32, "t"),
+                                          api._dev(w_m, torch.float32, "w"),
+                                          api._dev(s_m, torch.float32, "s"), api._stream())
+        assert r == 0
+
+    def sep_encode():
+        mapping()
+        Lp.encode()
+
+    def sep_decode():
+        mapping()
+        Lp.decode()
+
+    Lr.encode()
+    Lr.decode()
+    sep_encode()
+    sep_decode()
+    torch.cuda.synchronize()
+    Lr.verify()
+    Lp.verify()
+    assert torch.equal(Lr.off, Lp.off) and torch.equal(Lr.bs[: int(Lr.off[-1].item())],
+                                                        Lp.bs[: int(Lp.off[-1].item())])
+    t = {"fused_encode": time_events(Lr.encode, reps, stream),
+         "fused_decode": time_events(Lr.decode, reps, stream),
+         "separate_encode": time_events(sep_encode, reps, stream),
+         "separate_decode": time_events(sep_decode, reps, stream),
+         "mapping_pass": time_events(mapping, reps, stream)}
+    torch.cuda.synchronize()
+    Lr.verify()
+    Lp.verify()
+    out = {k + "_ms": round(v * 1e3, 4) for k, v in t.items()}
+    out["n"] = lat.n
+    out["fused_gain_encode"] = t["separate_encode"] / t["fused_encode"]
+    out["fused_gain_decode"] = t["separate_decode"] / t["fused_decode"]
+    # bytes of the separate pass: 2K planes read (logits, log-scales), 2K written
+    out["mapping_pass_GBps"] = 4 * cfgd.K * 4 * lat.n / t["mapping_pass"] / 1e9
+    return out
+
+
 def main():
     if len(sys.argv) > 2 and sys.argv[1] == "--summarize-prof":
         print(summarize_prof(sys.argv[2]))
@@ -364,10 +460,12 @@ def main():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="c3,c4,c5",
+    ap.add_argument("--forms", default="c3,c4,c5,table2,epilogue",
                     help="comma list of extra forms measured after the timed steps: c3 batch "
                          "of 64 latents; c4 4K latent plain vs learned bracket; c5 batch of "
-                         "256 K=5 latents, plain vs learned bracket; none")
+                         "256 K=5 latents, plain vs learned bracket; table2 Gaussian-CDF kinds "
+                         "of the paper's Table II on the Kodak-size latent; epilogue raw "
+                         "network outputs, fused vs separate mapping, 4K latent; none")
     ap.add_argument("--bracket-tuples", type=int, default=10_000_000,
                     help="training tuples of each bracket model (c4, c5)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -495,6 +593,10 @@ def main():
                                  sigma_max=c5.sigma_max, device=dev)
         forms["c5_batched_bracket"] = batched_form(api, synth, "c5", dev, reps=3,
                                                    bracket_model=m5, loop_baseline=False)
+    if "table2" in want:
+        forms["table2_cdf_kinds"] = table2_form(api, synth, dev)
+    if "epilogue" in want:
+        forms["raw_output_mapping"] = epilogue_form(api, synth, dev)
     if args.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB
         dst = torch.empty_like(src)
