@@ -323,7 +323,7 @@ int gmm_fast_recip_mismatches(uint64_t* count, void* stream);
 
 /* Raw network outputs to mixture parameters, one element per thread (the
  * entropy parameters come from a network, Sec. I and II-A; the scale lower
- * bound 0.11 is the one Sec. II-C quotes for scale tables). Planes [K][n]
+ * bound 0.11 is the one Sec. II-B quotes for scale tables). Planes [K][n]
  * [device]: weights = softmax over k of logits (differences to the largest
  * logit floored at -40.5, exp~ of the binary32 contract, sum in component
  * order, IEEE division); scales = max(exp~(clamp(log_scales, -7, 7)), 0.11).

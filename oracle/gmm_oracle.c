@@ -26,7 +26,7 @@
  *   - Sec. I and II-A: the mixture parameters come from a network; with
  *     param_kind 1 the inputs are its raw outputs (weight logits, means,
  *     log-scales), mapped here by a softmax and an exponential with the
- *     scale lower bound 0.11 that Sec. II-C quotes for scale tables.
+ *     scale lower bound 0.11 that Sec. II-B quotes for scale tables.
  * The paper fixes no float format, rANS word size, stream layout or CDF
  * quantization; the readings taken here (binary32 with a fixed operation
  * order, 32-bit state with 16-bit renormalisation, round-robin interleaved

@@ -9,7 +9,7 @@ and of the raw-output parameter mapping (no GPU).
   Table II: against libm's erfc and numpy's exp, symmetry, and the step
   monotonicity that follows from its error bound.
 - the raw-output mapping (softmax of weight logits, exponential of
-  log-scales with the 0.11 scale bound of Sec. II-C): against binary64.
+  log-scales with the 0.11 scale bound of Sec. II-B): against binary64.
 - coder plumbing: raw-output encode equals plain encode of mapped params;
   round trips and table invariants for every CDF kind.
 """
