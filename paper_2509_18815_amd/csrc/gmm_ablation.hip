@@ -72,7 +72,12 @@ void ablation_decode(const QCfg& q, int K, int kind, int P, int rounds, int L, i
                      int64_t S, const uint16_t* bs, int64_t total_words, const int64_t* offsets,
                      const float* w, const float* mu, const float* sg, int32_t* sym,
                      uint32_t* status, hipStream_t st) {
-  const int blk = (L == 1) ? 64 : 256;
+  // 256-thread workgroups: the four wavefronts of a workgroup land on the
+  // four SIMDs of a CU, while single-wavefront workgroups were measured to
+  // leave up to ~9% of the SIMDs with two wavefronts (and as many idle)
+  // after other work, which stretched a one-wavefront-per-SIMD decode by
+  // about 1.4x.
+  const int blk = 256;
   const int64_t threads = S * L;
   const dim3 grid((unsigned)((threads + blk - 1) / blk)), block(blk);
   dispatch_ablation(K, kind, [&](auto Kc, auto kc) {

@@ -331,7 +331,12 @@ int decode_launch(const gmm_cfg* cfg, int64_t n, const uint16_t* bs, int64_t tot
     hipLaunchKernelGGL(k_check_idx, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, idx, n,
                        n_total, status);
   const int64_t threads = S * L;
-  const int blk = (L == 1) ? 64 : 256;
+  // 256-thread workgroups: the four wavefronts of a workgroup land on the
+  // four SIMDs of a CU, while single-wavefront workgroups were measured to
+  // leave up to ~9% of the SIMDs with two wavefronts (and as many idle)
+  // after other work, which stretched a one-wavefront-per-SIMD decode by
+  // about 1.4x.
+  const int blk = 256;
   const dim3 grid((unsigned)((threads + blk - 1) / blk)), block(blk);
   if (cfg->cdf_kind >= 2) {
     if (idx) return GMM_EINVAL;
