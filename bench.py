@@ -164,15 +164,19 @@ def summarize_prof(root: str) -> str:
     return "\n".join(head + lines)
 
 
+# the sources the dominant kernel (the single-latent decode) is compiled from
+DOMINANT_SOURCES = ("gmm_device.h", "gmm_stream.h", "gmm_kernels.h", "gmm_coder.hip")
+
+
 def kernel_source_hash() -> str:
-    """sha256 of the HIP sources: counter figures recorded for one version
-    of the kernels are reported only while the sources are unchanged."""
-    import glob
+    """sha256 of the dominant kernel's HIP sources: counter figures recorded
+    for one version of the kernel are reported only while they are
+    unchanged."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2509_18815_amd", "csrc")
-    for f in sorted(glob.glob(os.path.join(csrc, "*"))):
-        h.update(open(f, "rb").read())
+    for f in DOMINANT_SOURCES:
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 

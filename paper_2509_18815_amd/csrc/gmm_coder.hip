@@ -195,6 +195,7 @@ QCfg make_qcfg(const gmm_cfg* c) {
   q.N = c->hi - c->lo + 1;
   q.M = 1u << c->precision;
   q.span = (float)(q.M - (uint32_t)q.N);
+  q.lo_mh = (float)c->lo - 0.5f;
   q.raw = c->param_kind;
   return q;
 }

@@ -221,6 +221,7 @@ struct QCfg {
   int32_t N;       // alphabet size
   uint32_t M;      // 2^P
   float span;      // (float)(M - N)
+  float lo_mh;     // (float)lo - 0.5, exact (|lo| <= 2^22)
   int32_t raw;     // 1: parameter planes hold raw outputs (weight logits, log-scales)
 };
 
@@ -307,7 +308,9 @@ __device__ __forceinline__ uint32_t cdf_inner(const Elem<K>& e, const QCfg& q, i
     F = __builtin_fmin(F, 1.0);
     return (uint32_t)j + (uint32_t)__builtin_floor(F * (double)(q.M - (uint32_t)q.N));
   }
-  const float b = (float)(q.lo + j) - 0.5f;
+  // (float)j + ((float)lo - 1/2) is the exact value lo + j - 1/2 (both
+  // terms and the sum are representable), i.e. the boundary b_j.
+  const float b = (float)j + q.lo_mh;
   float F = 0.0f;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -315,7 +318,8 @@ __device__ __forceinline__ uint32_t cdf_inner(const Elem<K>& e, const QCfg& q, i
     F = fma32(e.w[k], phi_tilde<kKind, kFastRecip>(z), F);
   }
   F = __builtin_fminf(F, 1.0f);
-  return (uint32_t)j + (uint32_t)__builtin_floorf(F * q.span);
+  // F >= 0 (w' >= 0 and Phi~ >= 0), so the truncating conversion is the floor
+  return (uint32_t)j + (uint32_t)(F * q.span);
 }
 
 // c_j for any j in [0, N] (c_0 = 0, c_N = M). The mixture is evaluated for
@@ -326,6 +330,21 @@ __device__ __forceinline__ uint32_t cdf_at(const Elem<K>& e, const QCfg& q, int3
   const uint32_t c = cdf_inner<K, kKind, kFastRecip>(e, q, j);
   const uint32_t lo_end = (j <= 0) ? 0u : c;
   return (j >= q.N) ? q.M : lo_end;
+}
+
+// c_j for j >= 1, with c_j = M for every j >= N (the padded upper part of a
+// power-of-two search range).
+template <int K, int kKind, bool kFastRecip>
+__device__ __forceinline__ uint32_t cdf_upper(const Elem<K>& e, const QCfg& q, int32_t j) {
+  const uint32_t c = cdf_inner<K, kKind, kFastRecip>(e, q, j);
+  return (j >= q.N) ? q.M : c;
+}
+
+// c_j for j in [0, N - 1].
+template <int K, int kKind, bool kFastRecip>
+__device__ __forceinline__ uint32_t cdf_lower(const Elem<K>& e, const QCfg& q, int32_t j) {
+  const uint32_t c = cdf_inner<K, kKind, kFastRecip>(e, q, j);
+  return (j <= 0) ? 0u : c;
 }
 
 // Device status bits, folded into a status code by the last kernel.

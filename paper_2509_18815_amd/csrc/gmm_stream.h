@@ -26,23 +26,25 @@ __device__ __forceinline__ int64_t gather_index(const int32_t* __restrict__ idx,
   return v < 0 ? 0 : (v >= n_total ? n_total - 1 : v);
 }
 
-// Branch-uniform binary search for the j with c_j <= slot < c_{j+1}:
-// exactly `rounds` = ceil(log2 N) CDF evaluations; on return c_lo = c_j and
-// c_hi = c_{j+1}. Once the interval holds one symbol, mid = lo re-evaluates
-// c_lo and changes nothing, so every lane runs the same instruction stream.
+// Branch-uniform binary search for the j with c_j <= slot < c_{j+1}, over
+// the power-of-two range [0, 2^rounds) with 2^rounds >= N and c_j = M for
+// every j >= N: round r tests lo + 2^(rounds-1-r), so every lane runs
+// exactly `rounds` CDF evaluations and the same instruction stream. Before
+// the round testing lo + h, c_lo = c(lo) <= slot < c_hi = c(lo + 2h), so
+// on return c_lo = c_j and c_hi = c_{j+1}; since slot < M, lo never reaches
+// N.
 template <int K, int kKind, bool kFast>
 __device__ __forceinline__ int32_t search_bs(const Elem<K>& e, const QCfg& q, int rounds,
                                              uint32_t slot, uint32_t& c_lo, uint32_t& c_hi) {
-  int32_t lo = 0, hi = q.N;
+  int32_t lo = 0;
   c_lo = 0;
   c_hi = q.M;
-  for (int r = 0; r < rounds; ++r) {
-    const int32_t mid = (lo + hi) >> 1;
-    const uint32_t c = cdf_at<K, kKind, kFast>(e, q, mid);
+  for (int r = rounds - 1; r >= 0; --r) {
+    const int32_t mid = lo + (1 << r);
+    const uint32_t c = cdf_upper<K, kKind, kFast>(e, q, mid);
     const bool right = slot >= c;
     lo = right ? mid : lo;
     c_lo = right ? c : c_lo;
-    hi = right ? hi : mid;
     c_hi = right ? c_hi : c;
   }
   return lo;
@@ -61,7 +63,7 @@ __device__ __forceinline__ int32_t search_group(const Elem<K>& e, const QCfg& q,
   for (int r = 0; r < rounds; ++r) {
     const uint32_t sz = (uint32_t)(hi - lo);
     const int32_t m = lo + (int32_t)((sz * (uint32_t)(g + 1)) / (uint32_t)(L + 1));
-    const uint32_t c = cdf_at<K, kKind, kFast>(e, q, m);
+    const uint32_t c = cdf_lower<K, kKind, kFast>(e, q, m);  // m < hi <= N
     const uint64_t bal = __ballot(slot >= c) & gmask;
     const int cnt = __popcll(bal);
     const int src_lo = gbase + (cnt > 0 ? cnt - 1 : 0);
