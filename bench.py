@@ -354,6 +354,42 @@ def bracket_single_form(api, synth, dev, model, reps=5):
             "training": model.history[-2:]}
 
 
+def bracket_few_streams_form(api, synth, dev, name, model, reps=10):
+    """A latent with few streams (the 320x48x32 latent at 4,096 streams, or
+    the 192x16x16 latent at 256 streams) decoded with 16 lanes per stream:
+    the plain 17-ary search against the group form of the learned bracket
+    (one 16-boundary round around the prediction), same bitstream."""
+    import torch
+    cfgd = synth.CONFIGS[name]
+    lat = synth.make_latents(cfgd, backend="torch", device=dev)[0]
+    L = Latent(api, cfgd, lat)
+    L.encode()
+    stream = torch.cuda.current_stream()
+    t_plain = time_events(L.decode, reps, stream)
+    br = model.load()
+    stats = torch.zeros(4, dtype=torch.int64, device=dev)
+    dec = torch.empty_like(L.dec)
+
+    def run(with_stats=False):
+        r = api.decode_into(L.cfg, L.bs, L.off, lat.weights, lat.means, lat.scales, dec,
+                            bracket=br, stats=stats if with_stats else None, ws=L.ws_dec,
+                            status=L.st[1:2])
+        assert r == 0
+    run(True)
+    torch.cuda.synchronize()
+    assert torch.equal(dec, lat.symbols), "bracket decode differs"
+    hits, misses, all_hit, steps = stats.cpu().tolist()
+    t_br = time_events(run, reps, stream)
+    torch.cuda.synchronize()
+    assert torch.equal(dec, lat.symbols) and L.st.tolist() == [0, 0]
+    br.close()
+    return {"shape": list(lat.shape), "n": L.n, "streams": L.S, "lanes_per_stream": 16,
+            "plain_decode_sym_s": L.n / t_plain, "bracket_decode_sym_s": L.n / t_br,
+            "plain_decode_ms": round(t_plain * 1e3, 4), "bracket_decode_ms": round(t_br * 1e3, 4),
+            "gain": t_plain / t_br, "hit_rate": hits / max(hits + misses, 1),
+            "wave_all_hit": all_hit / max(steps, 1)}
+
+
 # The paper's Table II (CPU, per 768x512 Kodak image; encode / decode ms),
 # quoted as context for the same comparison on one MI355X.
 PAPER_TABLE2_MS = {"no_approximation": (56.5, 127.0), "polya": (23.5, 34.3),
@@ -590,6 +626,13 @@ def main():
         m4 = train.train_bracket(c4.K, c4.lo, c4.hi, c4.precision, n_train=args.bracket_tuples,
                                  seed=synth.TRAIN_SEED_C4, device=dev)
         forms["c4_bracket"] = bracket_single_form(api, synth, dev, m4)
+        # the same model (same parameter distributions and support) on the
+        # Kodak-size latent, whose 4,096 streams decode with 16 lanes each
+        forms["c2a_bracket"] = bracket_few_streams_form(api, synth, dev, "c2a", m4)
+        c1 = synth.CONFIGS["c1"]
+        m1 = train.train_bracket(c1.K, c1.lo, c1.hi, c1.precision, n_train=args.bracket_tuples,
+                                 seed=synth.TRAIN_SEED_C1, device=dev)
+        forms["c1_bracket"] = bracket_few_streams_form(api, synth, dev, "c1", m1)
     if "c5" in want:
         c5 = synth.CONFIGS["c5"]
         m5 = train.train_bracket(c5.K, c5.lo, c5.hi, c5.precision, n_train=args.bracket_tuples,

@@ -313,7 +313,12 @@ int gmm_plan_destroy(gmm_plan* plan);
  * that many lanes share a stream and search (lanes+1)-ary, cutting the
  * sequential rounds to ceil(log_{lanes+1} N) at the cost of more total
  * evaluations (for latents with few streams); 0 (default) chooses from the
- * stream count. Output is identical for every choice. GMM_EINVAL otherwise. */
+ * stream count: the smallest power of two up to 32 that gives at least
+ * 65,536 lanes. With a bracket, 16 or more lanes select the group form
+ * (16 lanes per stream: the network's prediction seeds one round that
+ * evaluates 16 consecutive boundaries, with a 17-ary search as fallback),
+ * fewer the one-lane form (a verified bracket of radius R, then a binary
+ * search). Output is identical for every choice. GMM_EINVAL otherwise. */
 int gmm_set_decode_lanes(int32_t lanes);
 
 /* Diagnostic: number of floats u in [2^-10, 2^10] on which the coder's fused

@@ -1,8 +1,8 @@
 """Builds libflashgmm.so in-tree for gfx950 with hipcc.
 
 Every HIP source is compiled without FMA contraction (-ffp-contract=off: the
-CDF contract allows only explicit fused multiply-adds) and without packed
-FP32 instructions (-packed-fp32-ops).
+CDF contract allows only explicit fused multiply-adds), without packed FP32
+instructions (-packed-fp32-ops) and with matrix-core results in VGPRs.
 """
 from __future__ import annotations
 
@@ -18,9 +18,13 @@ LIB = os.path.join(HERE, "libflashgmm.so")
 OBJ = os.path.join(HERE, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+# Matrix-core results go straight to VGPRs (-amdgpu-mfma-vgpr-form): the
+# decoder's small networks read every accumulator right away, and the
+# accumulation-register form costs a copy per value.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-fno-fast-math", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wall", "-Wno-unused-function", "-I", os.path.join(HERE, "..", "include")]
+         "-mllvm", "-amdgpu-mfma-vgpr-form", "-Wall", "-Wno-unused-function", "-I",
+         os.path.join(HERE, "..", "include")]
 
 
 def _compile(src: str) -> str:

@@ -37,6 +37,14 @@ inline int phys_of_logical(int q) {
   return 8 * (t / 4) + 4 * hh + (t % 4);
 }
 
+// Physical hidden unit feeding logical input q (0..31) of k block kb of
+// layer 2 in the group form: the layer-1 accumulator rows of a lane in
+// 16x16 tiles 2 kb (inputs 0..3 of its group of eight) and 2 kb + 1 (4..7).
+inline int phys16(int kb, int q) {
+  const int kh = q / 8, e = q % 8;
+  return 32 * kb + (e < 4 ? 4 * kh + e : 16 + 4 * kh + (e - 4));
+}
+
 __global__ void k_fill_u32_bracket(uint32_t* p) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0u;
 }
@@ -54,6 +62,25 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
   unsigned long long cnt[4] = {0, 0, 0, 0};
   bracket_decode_wave<K, kKind, kFast>(q, P, n, S, (int64_t)blockIdx.x * 64, bs, total_words,
                                        offsets, w, mu, sg, sym, status, br, model, lds, cnt);
+  bracket_flush_stats(cnt, stats);
+}
+
+// Group form: 16 lanes per stream, four streams per wavefront.
+template <int K, int kKind, bool kFast>
+__global__ void __launch_bounds__(256)
+    k_decode_bracket_group(QCfg q, int P, int64_t n, int64_t S, const uint16_t* __restrict__ bs,
+                           int64_t total_words, const int64_t* __restrict__ offsets,
+                           const float* __restrict__ w, const float* __restrict__ mu,
+                           const float* __restrict__ sg, int32_t* __restrict__ sym,
+                           uint32_t* status, const BracketDev* __restrict__ br,
+                           unsigned long long* stats) {
+  const int64_t s0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64 * 4;
+  if (s0 >= S) return;  // whole wavefronts only
+  GroupModel gm;
+  load_group_model(br, gm);
+  unsigned long long cnt[4] = {0, 0, 0, 0};
+  bracket_group_decode<K, kKind, kFast>(q, P, n, S, s0, bs, total_words, offsets, w, mu, sg, sym,
+                                        status, br, gm, cnt);
   bracket_flush_stats(cnt, stats);
 }
 
@@ -91,18 +118,26 @@ namespace fgmm {
 int decode_bracket_launch(const gmm_cfg* cfg, int64_t n, const uint16_t* bs, int64_t total_words,
                           const int64_t* offsets, const float* w, const float* mu,
                           const float* sg, int32_t* symbols, const gmm_bracket* br,
-                          gmm_decode_stats* stats, uint32_t* status, bool fast, hipStream_t st) {
+                          gmm_decode_stats* stats, uint32_t* status, bool fast, hipStream_t st,
+                          int lanes) {
   if (!br || br->K != cfg->K) return GMM_EINVAL;
   const int64_t S = cfg->num_streams;
   const QCfg q = make_qcfg(cfg);
   hipLaunchKernelGGL(k_fill_u32_bracket, dim3(1), dim3(64), 0, st, status);
+  const int L = (lanes > 0) ? lanes : default_lanes_per_stream(S);
   dispatch(cfg->K, cfg->cdf_kind, fast, [&](auto Kc, auto kc, auto fc) {
     constexpr int K_ = decltype(Kc)::value;
     if constexpr (K_ <= 5) {
-      hipLaunchKernelGGL((k_decode_bracket<K_, decltype(kc)::value, decltype(fc)::value>),
-                         dim3((unsigned)((S + 63) / 64)), dim3(64), 0, st, q, cfg->precision, n,
-                         S, bs, total_words, offsets, w, mu, sg, symbols, status, br->dev,
-                         (unsigned long long*)stats);
+      if (L >= 16)
+        hipLaunchKernelGGL((k_decode_bracket_group<K_, decltype(kc)::value, decltype(fc)::value>),
+                           dim3((unsigned)((S + 15) / 16)), dim3(256), 0, st, q, cfg->precision,
+                           n, S, bs, total_words, offsets, w, mu, sg, symbols, status, br->dev,
+                           (unsigned long long*)stats);
+      else
+        hipLaunchKernelGGL((k_decode_bracket<K_, decltype(kc)::value, decltype(fc)::value>),
+                           dim3((unsigned)((S + 63) / 64)), dim3(64), 0, st, q, cfg->precision,
+                           n, S, bs, total_words, offsets, w, mu, sg, symbols, status, br->dev,
+                           (unsigned long long*)stats);
     }
   });
   return hipGetLastError() == hipSuccess ? GMM_OK : GMM_EDEVICE;
@@ -145,6 +180,42 @@ int gmm_bracket_create(const gmm_bracket_desc* d, gmm_bracket** out) {
         }
         pack(h.wa2[l][mb][kb], v);
       }
+    }
+  }
+  // group form (16x16x32 tiles): layer 1 takes raw inputs, so the input
+  // normalisation (x - mean) / std and the scalings of the log-scale inputs
+  // (ln s = -ln 2 log2(1 / s)) are folded into W1 and the bias, in binary64
+  std::vector<double> w1f((size_t)kMlpH * 17, 0.0);
+  for (int r = 0; r < kMlpH; ++r) {
+    double bias = b1[r];
+    for (int k = 0; k < D; ++k) {
+      const double inv = (d->in_std[k] > 0.0f) ? 1.0 / (double)d->in_std[k] : 0.0;
+      const double a = (k >= 2 * K && k < 3 * K) ? -M_LN2 : 1.0;
+      w1f[(size_t)r * 17 + k] = (double)W1[r * D + k] * inv * a;
+      bias -= (double)W1[r * D + k] * inv * (double)d->in_mean[k];
+    }
+    w1f[(size_t)r * 17 + 16] = bias;
+  }
+  for (int l = 0; l < 64; ++l) {
+    const int i = l % 16, kh = l / 16;
+    for (int t = 0; t < 4; ++t) {
+      const int row = 16 * t + i;
+      float v[8];
+      for (int e = 0; e < 8; ++e) {
+        const int k = 8 * kh + e;
+        v[e] = (k <= 16) ? (float)w1f[(size_t)row * 17 + k] : 0.0f;
+      }
+      pack(h.ga1[l][t], v);
+      for (int kb = 0; kb < 2; ++kb) {
+        for (int e = 0; e < 8; ++e) v[e] = W2[row * kMlpH + phys16(kb, 8 * kh + e)];
+        pack(h.ga2[l][t][kb], v);
+      }
+      for (int r = 0; r < 4; ++r) h.gb2[l][4 * t + r] = b2[16 * t + 4 * kh + r];
+    }
+    for (int kb = 0; kb < 2; ++kb) {
+      float v[8];
+      for (int e = 0; e < 8; ++e) v[e] = w3[phys16(kb, 8 * kh + e)];
+      pack(h.ga3[l][kb], v);
     }
   }
   for (int hh = 0; hh < 2; ++hh)

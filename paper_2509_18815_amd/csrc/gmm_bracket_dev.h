@@ -47,6 +47,24 @@ struct BracketDev {
   float b3, out_mean, out_std, pad0;
   float in_mean[16], in_inv_std[16];
   int32_t K, D, radius, pad1;
+  // Group form (v_mfma_f32_16x16x32_bf16, hidden units as rows in four
+  // 16-row tiles t, samples as columns). The input normalisation is folded
+  // into layer 1, which takes the element's raw inputs: the K flushed
+  // weights, the K means, the K values log2(1 / scale') (the reciprocals the
+  // CDF uses), slot / 2^P, and in input 16 a constant 1 that carries the
+  // folded bias. Lane l holds
+  //   ga1[l][t]: W1'[16 t + l % 16][8 (l / 16) + 2 w, +1], w = 0..3;
+  //   ga2[l][t][kb]: W2[16 t + l % 16][phys(kb, 8 (l / 16) + 2 w, +1)], the
+  //              physical hidden unit of logical input q of k block kb being
+  //              the layer-1 accumulator row that lane holds there;
+  //   ga3[l][kb]: w3[phys(kb, 8 (l / 16) + 2 w, +1)] (every row of the
+  //              layer-3 tile is w3, so every accumulator register of a
+  //              lane holds the output of its column);
+  //   gb2[l][4 t + r]: b2 of accumulator row 16 t + 4 (l / 16) + r.
+  uint32_t ga1[64][4][4];
+  uint32_t ga2[64][4][2][4];
+  uint32_t ga3[64][2][4];
+  float gb2[64][16];
 };
 
 // Per-wavefront LDS: the model's per-lane-half bias and output weights
@@ -341,6 +359,266 @@ __device__ __forceinline__ void bracket_decode_wave(
   }
   if (seg_ok && (x != (1u << 16) || ptr != b)) bad = true;
   if (bad) atomicOr(status, kStCorrupt);
+}
+
+// ---------------------------------------------------------------- group form
+// Streams with 16 lanes each (four per wavefront), for latents with few
+// streams, where the decode is bound by the latency of each stream's chain
+// of steps rather than by issue: the network runs on the matrix cores for
+// the wavefront's four samples (columns 0..3 of 16x16 tiles), then the 16
+// lanes of a stream evaluate the CDF at 16 consecutive boundaries around the
+// prediction in one round. If the slot lies between the first and the last
+// of them the symbol is known; otherwise the group finishes with the
+// 17-ary search over the side the slot fell on.
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
+struct GroupModel {
+  bf16x8 a1[4];
+  bf16x8 a2[4][2];
+  bf16x8 a3[2];
+  f32x4 b2[4];
+};
+
+__device__ __forceinline__ void load_group_model(const BracketDev* __restrict__ br,
+                                                 GroupModel& m) {
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    m.a1[t] = bracket_frag(br->ga1[l][t]);
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) m.a2[t][kb] = bracket_frag(br->ga2[l][t][kb]);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) m.b2[t][r] = br->gb2[l][4 * t + r];
+  }
+#pragma unroll
+  for (int kb = 0; kb < 2; ++kb) m.a3[kb] = bracket_frag(br->ga3[l][kb]);
+}
+
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// Two floats to a packed bfloat16 pair (round to nearest even), one
+// conversion instruction.
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+  const f32x2 f = {lo, hi};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, bf16x2));
+}
+
+// ReLU of a packed bfloat16 pair: as 16-bit integers, negative values
+// (sign bit set, -0 included) are below 0 and positive ones above, so an
+// integer max with 0 is the ReLU.
+__device__ __forceinline__ uint32_t relu_bf16x2(uint32_t v) {
+  const s16x2 x = __builtin_bit_cast(s16x2, v);
+  const s16x2 z = {0, 0};
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(x, z));
+}
+
+// Next layer's B operand from two accumulator tiles: inputs 0..3 of the
+// lane's group of eight from tile lo, 4..7 from tile hi, ReLU then bfloat16.
+__device__ __forceinline__ bf16x8 relu_operand(const f32x4& lo, const f32x4& hi) {
+  u32x4 v;
+  v[0] = relu_bf16x2(pack_bf16x2(lo[0], lo[1]));
+  v[1] = relu_bf16x2(pack_bf16x2(lo[2], lo[3]));
+  v[2] = relu_bf16x2(pack_bf16x2(hi[0], hi[1]));
+  v[3] = relu_bf16x2(pack_bf16x2(hi[2], hi[3]));
+  return __builtin_bit_cast(bf16x8, v);
+}
+
+// B operand of layer 1 (inputs as rows, samples as columns): lane l feeds
+// column c = l % 16 with inputs 8 (l / 16) .. 8 (l / 16) + 7. Column c < 4
+// is the sample of lane group c, whose lanes all hold its inputs x; lanes
+// 8..15 of a group serve inputs 8..15, lanes 0..7 inputs 0..7. Input 16 is
+// the constant 1 of the folded bias; columns 4..15 carry copies and are not
+// read.
+__device__ __forceinline__ bf16x8 group_operand(const float (&x)[16]) {
+  const int l = threadIdx.x & 63;
+  const bool upper = (l & 15) >= 8;
+  uint32_t wv[4];
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    // both halves packed with constant indices, then one select per word
+    const uint32_t lo = pack_bf16x2(x[2 * w], x[2 * w + 1]);
+    const uint32_t hi = pack_bf16x2(x[8 + 2 * w], x[9 + 2 * w]);
+    wv[w] = upper ? hi : lo;
+  }
+  const int kh = l >> 4;
+  const int src = 16 * (l & 3) + 8 * (kh & 1);
+  u32x4 rv;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) rv[w] = __shfl(wv[w], src, 64);
+  if (kh >= 2) {
+    rv[0] = (kh == 2) ? pack_bf16x2(1.0f, 0.0f) : 0u;
+    rv[1] = 0u;
+    rv[2] = 0u;
+    rv[3] = 0u;
+  }
+  return __builtin_bit_cast(bf16x8, rv);
+}
+
+// Network output for column l % 16 (every lane holds its column's value):
+// three layers on the matrix cores, ReLU between them on packed bfloat16.
+__device__ __forceinline__ float mlp_group(const BracketDev* __restrict__ br, const GroupModel& m,
+                                           const bf16x8& bx) {
+  const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+  f32x4 acc1[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+    acc1[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(m.a1[t], bx, zero, 0, 0, 0);
+  // k block kb of layer 2 takes rows 32 kb + 4 (l / 16) + 0..3 (tile 2 kb)
+  // and 32 kb + 16 + 4 (l / 16) + 0..3 (tile 2 kb + 1) of this lane
+  const bf16x8 op2[2] = {relu_operand(acc1[0], acc1[1]), relu_operand(acc1[2], acc1[3])};
+  f32x4 acc2[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    acc2[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(m.a2[t][0], op2[0], m.b2[t], 0, 0, 0);
+    acc2[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(m.a2[t][1], op2[1], acc2[t], 0, 0, 0);
+  }
+  const bf16x8 op3[2] = {relu_operand(acc2[0], acc2[1]), relu_operand(acc2[2], acc2[3])};
+  f32x4 acc3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(m.a3[0], op3[0], zero, 0, 0, 0);
+  acc3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(m.a3[1], op3[1], acc3, 0, 0, 0);
+  return fmaf(acc3[0] + br->b3, br->out_std, br->out_mean);
+}
+
+// Decodes streams s0 .. s0+3 of one latent, 16 lanes each (lane group
+// l / 16 takes stream s0 + l / 16). Every lane runs every step of the
+// wavefront's longest stream (finished groups compute on placeholder data
+// and store nothing): the matrix-core inference needs all 64 lanes.
+// Counters (lane 0 of each group): hit / miss symbols; lane 0 of the
+// wavefront also counts wavefront steps and steps on which every active
+// stream hit.
+template <int K, int kKind, bool kFast>
+__device__ __forceinline__ void bracket_group_decode(
+    const QCfg& q, int P, int64_t n, int64_t S, int64_t s0, const uint16_t* __restrict__ bs,
+    int64_t total_words, const int64_t* __restrict__ offsets, const float* __restrict__ w,
+    const float* __restrict__ mu, const float* __restrict__ sg, int32_t* __restrict__ sym,
+    uint32_t* status, const BracketDev* __restrict__ br, const GroupModel& gm,
+    unsigned long long (&cnt)[4]) {
+  constexpr int L = 16;
+  constexpr int kHalf = 7;  // window [p - 7, p + 8]: 16 boundaries, 15 symbols
+  const int l = threadIdx.x & 63;
+  const int gi = l >> 4, g = l & 15, gbase = l & 48;
+  const uint64_t gmask = 0xFFFFull << gbase;
+  const int64_t s = s0 + gi;
+  const int64_t ns_max = stream_len(n, S, s0);  // lower-index streams are never shorter
+  const int64_t ns = (s < S) ? stream_len(n, S, s) : 0;
+  bool seg_ok = false;
+  int64_t a = 0, b = 0;
+  if (s < S) {
+    a = offsets[s];
+    b = offsets[s + 1];
+    seg_ok = !(a < 0 || b < a + 2 || b > total_words);
+  }
+  bool bad = (s < S) && !seg_ok;
+  if (bad && g == 0)
+    for (int64_t p = 0; p < ns; ++p) sym[s + p * S] = q.lo;
+  uint32_t x = seg_ok ? ((uint32_t)bs[a] | ((uint32_t)bs[a + 1] << 16)) : (1u << 16);
+  int64_t ptr = a + 2;
+  const int64_t bl = seg_ok ? b - 1 : 0;  // last word of the segment (clamped reads)
+  uint32_t nword = (seg_ok && ptr < b) ? bs[ptr] : 0u;
+  if (seg_ok && x < (1u << 16)) bad = true;
+  const uint32_t mask = q.M - 1;
+  const float inv_m = 1.0f / (float)q.M;
+  const int64_t last = ns > 0 ? ns - 1 : 0;
+  // parameters one and two steps ahead (ring of two register sets); every
+  // load is unconditional, positions past the end reload the last element
+  constexpr int kRing = 2;
+  float rw[kRing][K], rm[kRing][K], rs[kRing][K];
+#pragma unroll
+  for (int d = 0; d < kRing; ++d) {
+    const int64_t pp = (d < last) ? d : last;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      rw[d][k] = 0.0f;
+      rm[d][k] = 0.0f;
+      rs[d][k] = 1.0f;
+    }
+    if (seg_ok && ns > 0) load_raw<K>(w, mu, sg, n, s + pp * S, rw[d], rm[d], rs[d]);
+  }
+  for (int64_t p0 = 0; p0 < ns_max; p0 += kRing) {
+#pragma unroll
+    for (int d = 0; d < kRing; ++d) {
+      const int64_t p = p0 + d;
+      if (p >= ns_max) break;
+      const bool act = seg_ok && p < ns;
+      float cw[K], cm[K], cs[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        cw[k] = opaque_copy(rw[d][k]);
+        cm[k] = opaque_copy(rm[d][k]);
+        cs[k] = opaque_copy(rs[d][k]);
+      }
+      const Elem<K> e = make_elem<K, kFast, kKind>(q, cw, cm, cs);
+      const uint32_t slot = x & mask;
+      // raw inputs (the normalisation is folded into layer 1)
+      float feat[16];
+#pragma unroll
+      for (int d = 0; d < 16; ++d) feat[d] = 0.0f;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        feat[k] = e.w[k];
+        feat[K + k] = e.mu[k];
+        feat[2 * K + k] = __builtin_amdgcn_logf(e.r[k]);  // log2(1 / scale')
+      }
+      feat[3 * K] = (float)slot * inv_m;
+      const float pred_col = mlp_group(br, gm, group_operand(feat));
+      const float pred = __shfl(pred_col, gi, 64);  // column gi = this group's sample
+      // window of 16 boundaries around the prediction, inside the indices
+      // [slot - (M - N), slot] that the quantization allows for this slot
+      const int32_t jmin = max(0, (int32_t)slot - (int32_t)(q.M - (uint32_t)q.N));
+      const int32_t jmax = min(q.N - 1, (int32_t)slot);
+      const float pc = __builtin_fminf(__builtin_fmaxf(pred - (float)q.lo, -1.0f), (float)q.N);
+      const int32_t jh = min(max((int32_t)__builtin_rintf(pc), jmin), jmax);
+      const int32_t ws = max(0, min(jh - kHalf, q.N - (L - 1)));
+      const uint32_t c = cdf_at<K, kKind, kFast>(e, q, ws + g);
+      const int cb = __popcll(__ballot(slot >= c) & gmask);  // c rises with g
+      const uint32_t c_l = __shfl(c, gbase + (cb > 0 ? cb - 1 : 0), 64);
+      const uint32_t c_h = __shfl(c, gbase + (cb < L ? cb : L - 1), 64);
+      const bool hit = cb > 0 && cb < L;
+      int32_t lo, hi;
+      uint32_t c_lo, c_hi;
+      if (hit) {
+        lo = ws + cb - 1; hi = lo + 1; c_lo = c_l; c_hi = c_h;
+      } else if (cb == 0) {
+        lo = 0; hi = ws; c_lo = 0; c_hi = c_h;
+      } else {
+        lo = ws + L - 1; hi = q.N; c_lo = c_l; c_hi = q.M;
+      }
+      if (!act) {
+        lo = 0; hi = 1; c_lo = 0; c_hi = q.M;
+      }
+      if (hi - lo > 1)  // uniform within the group
+        lo = search_group<K, kKind, kFast, L>(e, q, rounds_for(hi - lo, L), slot, g, gbase, gmask,
+                                              lo, hi, c_lo, c_hi);
+      const uint64_t lead = __ballot(g == 0 && act);
+      const uint64_t lead_hit = __ballot(g == 0 && act && hit);
+      if (g == 0) {
+        cnt[0] += (act && hit) ? 1 : 0;
+        cnt[1] += (act && !hit) ? 1 : 0;
+      }
+      if (l == 0 && lead) {
+        ++cnt[3];
+        if (lead_hit == lead) ++cnt[2];
+      }
+      if (act && g == 0) sym[s + p * S] = q.lo + lo;
+      // state update and refill as selects (all lanes of a group agree)
+      const uint32_t xs = (c_hi - c_lo) * (x >> P) + slot - c_lo;
+      const bool refill = act && xs < (1u << 16);
+      const bool have = ptr < b;
+      const uint32_t xr = refill ? ((xs << 16) | (have ? nword : 0u)) : xs;
+      x = act ? xr : x;
+      bad = bad || (refill && !have);
+      ptr += (refill && have) ? 1 : 0;
+      nword = seg_ok ? bs[ptr < b ? ptr : bl] : 0u;
+      asm volatile("" ::: "memory");  // keep the word's load ahead of the ring's
+      const int64_t pn = p + kRing;
+      if (seg_ok) load_raw<K>(w, mu, sg, n, s + (pn < last ? pn : last) * S, rw[d], rm[d], rs[d]);
+    }
+  }
+  if (seg_ok && (x != (1u << 16) || ptr != b)) bad = true;
+  if (bad && g == 0) atomicOr(status, kStCorrupt);
 }
 
 // Adds the wavefront's counters to stats[0..3] (one atomic each).

@@ -520,7 +520,7 @@ int gmm_decode(const gmm_cfg* cfg, int64_t n, const uint16_t* bitstream, int64_t
   int r;
   if (bracket) {
     r = fgmm::decode_bracket_launch(cfg, n, bitstream, total_words, offsets, w, mu, sg, symbols,
-                                    bracket, stats, (uint32_t*)wsp, fast, st);
+                                    bracket, stats, (uint32_t*)wsp, fast, st, g_lanes_override);
   } else {
     r = fgmm::decode_launch(cfg, n, bitstream, total_words, offsets, w, mu, sg, symbols,
                             (uint32_t*)wsp, fast, st, g_lanes_override, nullptr, 0);

@@ -29,7 +29,8 @@ int default_lanes_per_stream(int64_t S);
 int decode_bracket_launch(const gmm_cfg* cfg, int64_t n, const uint16_t* bs, int64_t total_words,
                           const int64_t* offsets, const float* w, const float* mu,
                           const float* sg, int32_t* symbols, const gmm_bracket* bracket,
-                          gmm_decode_stats* stats, uint32_t* status, bool fast, hipStream_t st);
+                          gmm_decode_stats* stats, uint32_t* status, bool fast, hipStream_t st,
+                          int lanes);
 
 // Launchers of the Polya (kind 2) and binary64-reference (kind 3) CDF
 // kernels (gmm_ablation.hip); launch errors are left for hipGetLastError.

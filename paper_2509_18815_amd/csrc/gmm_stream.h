@@ -105,10 +105,18 @@ __device__ __forceinline__ uint32_t enc_cdf_elem(const QCfg& q, int64_t n, int64
   return (c0 << 16) | (c1 - c0);
 }
 
+// s_waitcnt immediate: vector memory count 0, the other counters unlimited.
+constexpr int kWaitVm0 = 0x0F70;
+
 // Encode phase 2 for stream s: the integer rANS recurrence over the packed
 // (c, f) words cf[s + p S], p = n_s-1 .. 0. The k-th emitted word goes to
 // region_end[-k], so the words end up in the order the decoder reads them.
 // Returns the final state; *count receives the number of words.
+//
+// Memory operations are arranged so that every wait is for work issued a
+// whole block of kDepth steps earlier: the (c, f) words are loaded a block
+// ahead with a fixed number of loads, and the words a block emits are held
+// in registers and stored at the start of the next block.
 __device__ __forceinline__ uint32_t rans_stream(int64_t n, int64_t S, int P, int64_t s,
                                                 const uint32_t* __restrict__ cf,
                                                 uint16_t* __restrict__ region_end,
@@ -117,36 +125,73 @@ __device__ __forceinline__ uint32_t rans_stream(int64_t n, int64_t S, int P, int
   uint32_t x = 1u << 16;
   uint32_t cnt = 0;
   const int shift = 32 - P;
-  // (c, f) words are fetched kDepth steps ahead of the dependent chain
+  // the word of position p sits at s + p S, walked down by running indices
   constexpr int kDepth = 8;
-  uint32_t buf[kDepth];
+  int64_t dS[kDepth];
 #pragma unroll
-  for (int d = 0; d < kDepth; ++d) {
-    const int64_t pp = ns - 1 - d;
-    buf[d] = (pp >= 0) ? cf[s + pp * S] : 0u;
-  }
+  for (int d = 0; d < kDepth; ++d) dS[d] = (int64_t)d * S;
+  uint32_t buf[kDepth];
+  int64_t base = s + (ns - 1) * S;  // position ns - 1
+#pragma unroll
+  for (int d = 0; d < kDepth; ++d) buf[d] = (ns - 1 - d >= 0) ? cf[base - dS[d]] : 0u;
+  const int64_t step = (int64_t)kDepth * S;
+  uint32_t pend[kDepth];   // words emitted by the previous block (bit d of pmask: step d emitted)
+  uint32_t pmask = 0, pbase = 0;
   for (int64_t p = ns - 1; p >= 0; p -= kDepth) {
+    base -= step;  // position p - kDepth
+    // everything issued so far is a block old: the loads of this block's
+    // words and the previous block's stores (a wait issued after the new
+    // stores and loads would also wait for them, the counter being shared)
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
     uint32_t cur[kDepth];
 #pragma unroll
+    for (int d = 0; d < kDepth; ++d) cur[d] = buf[d];
+#pragma unroll
+    for (int d = 0; d < kDepth; ++d)
+      if ((pmask >> d) & 1u)
+        region_end[-(int64_t)(pbase + __builtin_popcount(pmask & ((1u << d) - 1u)))] =
+            (uint16_t)pend[d];
+    pbase = cnt;
+    pmask = 0;
+    asm volatile("" ::: "memory");
+#pragma unroll
     for (int d = 0; d < kDepth; ++d) {
-      cur[d] = buf[d];
-      const int64_t pp = p - kDepth - d;
-      buf[d] = (pp >= 0) ? cf[s + pp * S] : 0u;
+      // unconditional (positions below 0 reload position 0)
+      const int64_t at = base - dS[d];
+      buf[d] = cf[at >= s ? at : s];
     }
 #pragma unroll
     for (int d = 0; d < kDepth; ++d) {
       if (p - d < 0) break;
       const uint32_t c = cur[d] >> 16;
       const uint32_t f = cur[d] & 0xFFFFu;
-      if (x >= (f << shift)) {
-        region_end[-(int64_t)cnt] = (uint16_t)(x & 0xFFFFu);
-        ++cnt;
-        x >>= 16;
-      }
-      const uint32_t qd = x / f;
-      x = (qd << P) + (x - qd * f) + c;
+      // 1/f in binary64 off the chain: hardware estimate, one Newton step
+      const double fd = (double)f;
+      const double y0 = __builtin_amdgcn_rcp(fd);
+      const double rf = __builtin_fma(__builtin_fma(-fd, y0, 1.0), y0, y0);
+      const bool emit = x >= (f << shift);
+      pend[d] = x & 0xFFFFu;
+      pmask |= (emit ? 1u : 0u) << d;
+      cnt += emit ? 1u : 0u;
+      x = emit ? (x >> 16) : x;
+      // x <- (x div f) 2^P + (x mod f) + c, exactly: with rf within 2^-50 of
+      // 1/f, x rf is within 2^-17 of x / f < 2^32, while a non-integer
+      // x / f lies at least 1/f >= 2^-16 below the next integer, so
+      // q0 = trunc(x rf) is the quotient q or q - 1; then r0 = x - q0 f
+      // (exact) is the remainder or the remainder + f, and one comparison
+      // fixes both. Every binary64 value here is an integer below 2^53.
+      const double xd = (double)x;
+      const double q0 = __builtin_trunc(xd * rf);
+      const double r0 = __builtin_fma(-q0, fd, xd);
+      const double fix = (r0 >= fd) ? (double)((1u << P) - f) : 0.0;
+      x = (uint32_t)(__builtin_fma(q0, (double)(1u << P), r0 + (double)c) + fix);
     }
   }
+#pragma unroll
+  for (int d = 0; d < kDepth; ++d)
+    if ((pmask >> d) & 1u)
+      region_end[-(int64_t)(pbase + __builtin_popcount(pmask & ((1u << d) - 1u)))] =
+          (uint16_t)pend[d];
   *count = cnt;
   return x;
 }
@@ -226,6 +271,14 @@ __device__ __forceinline__ void pack_segment(uint16_t* __restrict__ dst, uint32_
   }
 }
 
+// Register copy the compiler cannot coalesce away (an early-clobber output
+// never shares a register with the input).
+__device__ __forceinline__ float opaque_copy(float v) {
+  float r;
+  asm volatile("v_mov_b32 %0, %1" : "=&v"(r) : "v"(v));
+  return r;
+}
+
 // Decode of stream s of one latent by one lane (binary search) or by a
 // group of L lanes ((L+1)-ary search); lane g == 0 of the group writes the
 // symbols. The next element's parameters and the next renormalisation word
@@ -235,14 +288,6 @@ __device__ __forceinline__ void pack_segment(uint16_t* __restrict__ dst, uint32_
 // With kGather the coded sequence is the subset idx[0..n) of a latent of
 // n_total elements: pass position i reads its parameters at element idx[i]
 // of the [K][n_total] planes and writes its symbol to sym[idx[i]].
-// Register copy the compiler cannot coalesce away (an early-clobber output
-// never shares a register with the input).
-__device__ __forceinline__ float opaque_copy(float v) {
-  float r;
-  asm volatile("v_mov_b32 %0, %1" : "=&v"(r) : "v"(v));
-  return r;
-}
-
 template <int K, int kKind, bool kFast, int L, bool kGather = false>
 __device__ __forceinline__ bool decode_stream(const QCfg& q, int P, int rounds, int64_t n,
                                               int64_t S, int64_t s, int g,

@@ -75,6 +75,7 @@ CONFIGS = {
 }
 TRAIN_SEED_C4 = 6
 TRAIN_SEED_C5 = 8
+TRAIN_SEED_C1 = 9
 
 
 @dataclass

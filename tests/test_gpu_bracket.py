@@ -177,7 +177,18 @@ def test_bracket_decode_bit_exact_and_gain(api, orc, trained):
     bad.close()
 
 
-def test_bracket_decode_matches_oracle_on_corruption(api, orc, trained):
+@pytest.fixture
+def lanes(api, request):
+    """Lanes per stream for the call (0: the library's choice); reset after."""
+    api.set_decode_lanes(request.param)
+    yield request.param
+    api.set_decode_lanes(0)
+
+
+@pytest.mark.parametrize("lanes", [0, 1, 16], indirect=True)
+def test_bracket_decode_matches_oracle_on_corruption(api, orc, trained, lanes):
+    """333 streams: the group form (16 lanes per stream, partial last
+    wavefront) by default and with 16 lanes, the one-lane form with 1."""
     br = trained.load()
     rng = np.random.default_rng(11)
     n, K, S = 20000, 3, 333
@@ -198,6 +209,62 @@ def test_bracket_decode_matches_oracle_on_corruption(api, orc, trained):
         assert gst == ost
         assert np.array_equal(dec.cpu().numpy(), osym)
     br.close()
+
+
+def test_group_bracket_decode_kodak_latent(api, orc, trained):
+    """The 320x48x32 latent at 4,096 streams decodes with 16 lanes per stream:
+    the group form of the bracket (matrix-core inference for four streams
+    per wavefront, one 16-boundary window round) is bit-identical to the
+    plain decode; a trained model hits on nearly every symbol (which also
+    checks the 16x16x32 operand layout: a wrong layout predicts noise); an
+    untrained one misses and takes the fallback search everywhere."""
+    cfgd = synth.CONFIGS["c2a"]
+    lat = synth.make_latents(cfgd, backend="torch", device="cuda")[0]
+    S = lat.streams
+    assert S == 4096
+    bs, off = api.encode(lat.symbols, lat.weights, lat.means, lat.scales, cfgd.lo, cfgd.hi, 16, S)
+    cfg = api.make_cfg(3, cfgd.lo, cfgd.hi, 16, S)
+    br = trained.load()
+    dec = torch.empty(lat.n, dtype=torch.int32, device="cuda")
+    stats = torch.zeros(4, dtype=torch.int64, device="cuda")
+    assert api.decode_into(cfg, bs, off, lat.weights, lat.means, lat.scales, dec, bracket=br,
+                           stats=stats) == api.OK
+    assert torch.equal(dec, lat.symbols)
+    hits, misses, all_hit, steps = stats.cpu().tolist()
+    assert hits + misses == lat.n
+    assert hits / lat.n > 0.97, hits / lat.n
+    rng = np.random.default_rng(19)
+    bad = api.Bracket(3, rand_net(rng, 10, orc, 1.0), trained.in_mean, trained.in_std, 0.0, 50.0)
+    stats.zero_()
+    dec.fill_(-9)
+    assert api.decode_into(cfg, bs, off, lat.weights, lat.means, lat.scales, dec, bracket=bad,
+                           stats=stats) == api.OK
+    assert torch.equal(dec, lat.symbols)
+    h2, m2, _, _ = stats.cpu().tolist()
+    assert h2 + m2 == lat.n and m2 > 0
+    st = torch.cuda.current_stream()
+
+    def timed(fn, reps=10):
+        fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        for _ in range(reps):
+            fn()
+        b.record(st)
+        b.synchronize()
+        return a.elapsed_time(b) / reps
+    st_d = torch.zeros(1, dtype=torch.int32, device="cuda")
+    t_plain = timed(lambda: api.decode_into(cfg, bs, off, lat.weights, lat.means, lat.scales,
+                                            dec, status=st_d))
+    t_br = timed(lambda: api.decode_into(cfg, bs, off, lat.weights, lat.means, lat.scales,
+                                         dec, bracket=br, status=st_d))
+    torch.cuda.synchronize()
+    assert st_d.item() == 0 and torch.equal(dec, lat.symbols)
+    print(f"group bracket (320x48x32, 4096 streams): hit rate {hits / lat.n:.4f}, all-hit "
+          f"wavefront steps {all_hit / steps:.3f}, untrained hit rate {h2 / lat.n:.3f}, "
+          f"plain {t_plain:.4f} ms, bracket {t_br:.4f} ms, gain {t_plain / t_br:.3f}x")
+    br.close()
+    bad.close()
 
 
 def _plan_io(lats, S_list, api, lo, hi):
@@ -240,10 +307,12 @@ def test_batched_bracket_every_candidate(api, trained):
     br.close()
 
 
-def test_k5_bracket_and_cooperative_fallback(api, orc):
-    """A briefly trained K = 5 model (many misses, so the cooperative
-    fallback runs with every group size) decodes bit-exactly, single latent
-    and batched, and matches the oracle on a small latent."""
+@pytest.mark.parametrize("lanes", [0, 1], indirect=True)
+def test_k5_bracket_and_cooperative_fallback(api, orc, lanes):
+    """A briefly trained K = 5 model (many misses, so the fallback searches
+    run: the one-lane form's cooperative fallback with every group size, the
+    group form's 17-ary search) decodes bit-exactly, and matches the oracle
+    on a small latent."""
     from paper_2509_18815_amd import train
     cfgd = synth.CONFIGS["c5"]
     model = train.train_bracket(5, cfgd.lo, cfgd.hi, 16, n_train=131072, n_eval=16384,
