@@ -71,7 +71,7 @@ void ablation_enc_cdf(const QCfg& q, int K, int kind, int64_t n, const int32_t* 
 void ablation_decode(const QCfg& q, int K, int kind, int P, int rounds, int L, int64_t n,
                      int64_t S, const uint16_t* bs, int64_t total_words, const int64_t* offsets,
                      const float* w, const float* mu, const float* sg, int32_t* sym,
-                     uint32_t* status, hipStream_t st) {
+                     uint32_t* status, int32_t* dev_status, hipStream_t st) {
   // 256-thread workgroups: the four wavefronts of a workgroup land on the
   // four SIMDs of a CU, while single-wavefront workgroups were measured to
   // leave up to ~9% of the SIMDs with two wavefronts (and as many idle)
@@ -84,12 +84,12 @@ void ablation_decode(const QCfg& q, int K, int kind, int P, int rounds, int L, i
     constexpr int K_ = decltype(Kc)::value, KI = decltype(kc)::value;
     if (L == 1)
       hipLaunchKernelGGL((k_decode<K_, KI, false, 1, false>), grid, block, 0, st, q, P, rounds, n,
-                         S, bs, total_words, offsets, w, mu, sg, sym, status, nullptr,
-                         (int64_t)0);
+                         S, bs, total_words, offsets, w, mu, sg, sym, status, dev_status,
+                         nullptr, (int64_t)0);
     else
       hipLaunchKernelGGL((k_decode<K_, KI, false, 16, false>), grid, block, 0, st, q, P, rounds,
-                         n, S, bs, total_words, offsets, w, mu, sg, sym, status, nullptr,
-                         (int64_t)0);
+                         n, S, bs, total_words, offsets, w, mu, sg, sym, status, dev_status,
+                         nullptr, (int64_t)0);
   });
 }
 

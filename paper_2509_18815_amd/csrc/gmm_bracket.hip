@@ -45,8 +45,9 @@ inline int phys16(int kb, int q) {
   return 32 * kb + (e < 4 ? 4 * kh + e : 16 + 4 * kh + (e - 4));
 }
 
+// Zeroes the status bits and the workgroup counter.
 __global__ void k_fill_u32_bracket(uint32_t* p) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0u;
+  if (threadIdx.x < 2 && blockIdx.x == 0) p[threadIdx.x] = 0u;
 }
 
 template <int K, int kKind, bool kFast>
@@ -55,7 +56,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
                      int64_t total_words, const int64_t* __restrict__ offsets,
                      const float* __restrict__ w, const float* __restrict__ mu,
                      const float* __restrict__ sg, int32_t* __restrict__ sym, uint32_t* status,
-                     const BracketDev* __restrict__ br, unsigned long long* stats) {
+                     const BracketDev* __restrict__ br, unsigned long long* stats,
+                     int32_t* dev_status) {
   __shared__ BracketLds lds;
   LaneModel model;
   load_lane_model(br, model, lds);
@@ -63,6 +65,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
   bracket_decode_wave<K, kKind, kFast>(q, P, n, S, (int64_t)blockIdx.x * 64, bs, total_words,
                                        offsets, w, mu, sg, sym, status, br, model, lds, cnt);
   bracket_flush_stats(cnt, stats);
+  grid_finish_status(status, dev_status);
 }
 
 // Group form: 16 lanes per stream, four streams per wavefront.
@@ -73,15 +76,17 @@ __global__ void __launch_bounds__(256)
                            const float* __restrict__ w, const float* __restrict__ mu,
                            const float* __restrict__ sg, int32_t* __restrict__ sym,
                            uint32_t* status, const BracketDev* __restrict__ br,
-                           unsigned long long* stats) {
+                           unsigned long long* stats, int32_t* dev_status) {
   const int64_t s0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64 * 4;
-  if (s0 >= S) return;  // whole wavefronts only
-  GroupModel gm;
-  load_group_model(br, gm);
-  unsigned long long cnt[4] = {0, 0, 0, 0};
-  bracket_group_decode<K, kKind, kFast>(q, P, n, S, s0, bs, total_words, offsets, w, mu, sg, sym,
-                                        status, br, gm, cnt);
-  bracket_flush_stats(cnt, stats);
+  if (s0 < S) {  // whole wavefronts
+    GroupModel gm;
+    load_group_model(br, gm);
+    unsigned long long cnt[4] = {0, 0, 0, 0};
+    bracket_group_decode<K, kKind, kFast>(q, P, n, S, s0, bs, total_words, offsets, w, mu, sg,
+                                          sym, status, br, gm, cnt);
+    bracket_flush_stats(cnt, stats);
+  }
+  grid_finish_status(status, dev_status);
 }
 
 template <int K>
@@ -119,7 +124,7 @@ int decode_bracket_launch(const gmm_cfg* cfg, int64_t n, const uint16_t* bs, int
                           const int64_t* offsets, const float* w, const float* mu,
                           const float* sg, int32_t* symbols, const gmm_bracket* br,
                           gmm_decode_stats* stats, uint32_t* status, bool fast, hipStream_t st,
-                          int lanes) {
+                          int lanes, int32_t* dev_status) {
   if (!br || br->K != cfg->K) return GMM_EINVAL;
   const int64_t S = cfg->num_streams;
   const QCfg q = make_qcfg(cfg);
@@ -132,12 +137,12 @@ int decode_bracket_launch(const gmm_cfg* cfg, int64_t n, const uint16_t* bs, int
         hipLaunchKernelGGL((k_decode_bracket_group<K_, decltype(kc)::value, decltype(fc)::value>),
                            dim3((unsigned)((S + 15) / 16)), dim3(256), 0, st, q, cfg->precision,
                            n, S, bs, total_words, offsets, w, mu, sg, symbols, status, br->dev,
-                           (unsigned long long*)stats);
+                           (unsigned long long*)stats, dev_status);
       else
         hipLaunchKernelGGL((k_decode_bracket<K_, decltype(kc)::value, decltype(fc)::value>),
                            dim3((unsigned)((S + 63) / 64)), dim3(64), 0, st, q, cfg->precision,
                            n, S, bs, total_words, offsets, w, mu, sg, symbols, status, br->dev,
-                           (unsigned long long*)stats);
+                           (unsigned long long*)stats, dev_status);
     }
   });
   return hipGetLastError() == hipSuccess ? GMM_OK : GMM_EDEVICE;

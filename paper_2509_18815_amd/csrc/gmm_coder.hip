@@ -36,18 +36,6 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t count) {
   if (i < count) p[i] = v;
 }
 
-// Folds status bits into the call's status code.
-__global__ void k_finalize(const uint32_t* bits, int32_t* dev_status) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    const uint32_t b = *bits;
-    int32_t code = GMM_OK;
-    if (b & kStInval) code = GMM_EINVAL;
-    else if (b & kStRange) code = GMM_ERANGE;
-    else if (b & kStNoSpace) code = GMM_ENOSPC;
-    else if (b & kStCorrupt) code = GMM_ECORRUPT;
-    *dev_status = code;
-  }
-}
 
 // Exhaustive check of recip_fast against IEEE division on every float in
 // [lo_bits, lo_bits + count).
@@ -65,11 +53,15 @@ constexpr int kRansBlock = 256;
 // Encode phase 2: one lane per stream; stream s owns scratch words
 // [s cap, (s+1) cap). Then the block's exclusive scan of the segment
 // lengths 2 + count (the wavefront prefix sums that place the streams).
+// The workgroup that finishes last scans the block totals into blk_pre,
+// flags a total above the capacity, and writes the call's status code
+// (bits[0]: status bits, bits[1]: workgroup counter, zeroed before).
 __global__ void __launch_bounds__(kRansBlock)
     k_enc_rans(int64_t n, int64_t S, int P, const uint32_t* __restrict__ cf,
                uint16_t* __restrict__ scratch, int64_t cap, uint32_t* __restrict__ xfin,
                uint32_t* __restrict__ count, uint32_t* __restrict__ local_off,
-               int64_t* __restrict__ blk_total) {
+               int64_t* __restrict__ blk_total, int64_t* __restrict__ blk_pre, int64_t capacity,
+               uint32_t* bits, int32_t* dev_status) {
   const int64_t s = (int64_t)blockIdx.x * kRansBlock + threadIdx.x;
   uint32_t cnt = 0;
   if (s < S) {
@@ -79,12 +71,14 @@ __global__ void __launch_bounds__(kRansBlock)
   uint32_t tot;
   const uint32_t excl = block_excl_scan<kRansBlock>((s < S) ? cnt + 2u : 0u, &tot);
   if (s < S) local_off[s] = excl;
-  if (threadIdx.x == 0) blk_total[blockIdx.x] = tot;
-}
-
-__global__ void __launch_bounds__(kScanBlock)
-    k_scan_blk(int64_t nblk, const int64_t* __restrict__ tot, int64_t* __restrict__ pre) {
-  scan_totals(nblk, tot, pre);
+  if (threadIdx.x == 0) atomicExch((unsigned long long*)(blk_total + blockIdx.x), (unsigned long long)tot);
+  if (!grid_last_block(bits + 1)) return;
+  const int64_t total = scan_totals<kRansBlock, true>(gridDim.x, blk_total, blk_pre);
+  if (threadIdx.x == 0) {
+    uint32_t b = atomicOr(bits, (total > capacity) ? kStNoSpace : 0u);
+    if (total > capacity) b |= kStNoSpace;
+    if (dev_status) *dev_status = status_code(b);
+  }
 }
 
 // Offsets and compaction: 16 lanes per stream.
@@ -94,12 +88,11 @@ __global__ void __launch_bounds__(kPackBlock)
            const uint32_t* __restrict__ xfin, const uint32_t* __restrict__ count,
            const uint32_t* __restrict__ local_off, const int64_t* __restrict__ blk_pre,
            const int64_t* __restrict__ blk_total, int64_t* __restrict__ offsets,
-           uint16_t* __restrict__ bitstream, int64_t capacity, uint32_t* status) {
+           uint16_t* __restrict__ bitstream, int64_t capacity) {
   const int64_t s = (int64_t)blockIdx.x * (kPackBlock / kPackLanes) + threadIdx.x / kPackLanes;
   const int l = threadIdx.x % kPackLanes;
   const int64_t total = blk_pre[nblk - 1] + blk_total[nblk - 1];
-  const bool fits = total <= capacity;
-  if (!fits && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(status, kStNoSpace);
+  const bool fits = total <= capacity;  // (k_enc_rans flagged ENOSPC)
   if (s >= S) return;
   const int64_t off = blk_pre[s / kRansBlock] + (int64_t)local_off[s];
   const uint32_t cnt = count[s];
@@ -240,10 +233,9 @@ bool use_fast_recip(hipStream_t st) {
 }
 
 int finish(uint32_t* bits, int32_t* dev_status, hipStream_t st) {
-  if (dev_status) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, bits, dev_status);
-    return hipGetLastError() == hipSuccess ? GMM_OK : GMM_EDEVICE;
-  }
+  // with a device status the last workgroup of the call's last kernel has
+  // written the code already
+  if (dev_status) return GMM_OK;
   uint32_t h = 0;
   if (hipMemcpyAsync(&h, bits, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess)
     return GMM_EDEVICE;
@@ -259,7 +251,7 @@ int finish(uint32_t* bits, int32_t* dev_status, hipStream_t st) {
 int encode_launch(const gmm_cfg* cfg, int64_t n, const int32_t* symbols, const float* w,
                   const float* mu, const float* sg, uint16_t* bitstream, int64_t capacity,
                   int64_t* offsets, char* ws, bool fast, hipStream_t st, const int32_t* idx,
-                  int64_t n_total) {
+                  int64_t n_total, int32_t* dev_status) {
   const int64_t S = cfg->num_streams;
   const EncLayout L = enc_layout(n, S);
   const QCfg q = make_qcfg(cfg);
@@ -271,7 +263,8 @@ int encode_launch(const gmm_cfg* cfg, int64_t n, const int32_t* symbols, const f
   uint32_t* local_off = (uint32_t*)(ws + L.local_off);
   int64_t* blk_total = (int64_t*)(ws + L.blk_total);
   int64_t* blk_pre = (int64_t*)(ws + L.blk_pre);
-  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, status, 0u, (int64_t)1);
+  // status bits and the workgroup counter of k_enc_rans
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, status, 0u, (int64_t)2);
   if (n > 0) {
     const dim3 grid((unsigned)((n + 255) / 256)), block(256);
     if (idx) hipLaunchKernelGGL(k_check_idx, grid, block, 0, st, idx, n, n_total, status);
@@ -290,12 +283,12 @@ int encode_launch(const gmm_cfg* cfg, int64_t n, const int32_t* symbols, const f
     });
   }
   hipLaunchKernelGGL(k_enc_rans, dim3((unsigned)L.nblk), dim3(kRansBlock), 0, st, n, S,
-                     cfg->precision, cf, scratch, L.cap, xfin, count, local_off, blk_total);
-  hipLaunchKernelGGL(k_scan_blk, dim3(1), dim3(kScanBlock), 0, st, L.nblk, blk_total, blk_pre);
+                     cfg->precision, cf, scratch, L.cap, xfin, count, local_off, blk_total,
+                     blk_pre, capacity, status, dev_status);
   const int64_t per = kPackBlock / kPackLanes;
   hipLaunchKernelGGL(k_pack, dim3((unsigned)((S + per - 1) / per)), dim3(kPackBlock), 0, st, S,
                      L.nblk, L.cap, scratch, xfin, count, local_off, blk_pre, blk_total, offsets,
-                     bitstream, capacity, status);
+                     bitstream, capacity);
   return hipGetLastError() == hipSuccess ? GMM_OK : GMM_EDEVICE;
 }
 
@@ -321,13 +314,13 @@ int default_lanes_per_stream(int64_t S) {
 int decode_launch(const gmm_cfg* cfg, int64_t n, const uint16_t* bs, int64_t total_words,
                   const int64_t* offsets, const float* w, const float* mu, const float* sg,
                   int32_t* symbols, uint32_t* status, bool fast, hipStream_t st, int lanes,
-                  const int32_t* idx, int64_t n_total) {
+                  const int32_t* idx, int64_t n_total, int32_t* dev_status) {
   const int64_t S = cfg->num_streams;
   const QCfg q = make_qcfg(cfg);
   int L = (lanes > 0) ? lanes : default_lanes_per_stream(S);
   if (cfg->cdf_kind >= 2) L = (L == 1) ? 1 : 16;  // the comparison kinds build L = 1 and 16
   const int rounds = (L == 1) ? search_rounds(q.N) : search_rounds_lps(q.N, L);
-  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, status, 0u, (int64_t)1);
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, status, 0u, (int64_t)2);
   if (idx && n > 0)
     hipLaunchKernelGGL(k_check_idx, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, idx, n,
                        n_total, status);
@@ -342,7 +335,7 @@ int decode_launch(const gmm_cfg* cfg, int64_t n, const uint16_t* bs, int64_t tot
   if (cfg->cdf_kind >= 2) {
     if (idx) return GMM_EINVAL;
     ablation_decode(q, cfg->K, cfg->cdf_kind, cfg->precision, rounds, L, n, S, bs, total_words,
-                    offsets, w, mu, sg, symbols, status, st);
+                    offsets, w, mu, sg, symbols, status, dev_status, st);
     return hipGetLastError() == hipSuccess ? GMM_OK : GMM_EDEVICE;
   }
   dispatch(cfg->K, cfg->cdf_kind, fast, [&](auto Kc, auto kc, auto fc) {
@@ -351,12 +344,12 @@ int decode_launch(const gmm_cfg* cfg, int64_t n, const uint16_t* bs, int64_t tot
 #define FG_DEC(LL)                                                                              \
   if (idx)                                                                                      \
     hipLaunchKernelGGL((k_decode<K_, KI, F, LL, true>), grid, block, 0, st, q, cfg->precision,  \
-                       rounds, n, S, bs, total_words, offsets, w, mu, sg, symbols, status, idx, \
-                       n_total);                                                                \
+                       rounds, n, S, bs, total_words, offsets, w, mu, sg, symbols, status,      \
+                       dev_status, idx, n_total);                                               \
   else                                                                                          \
     hipLaunchKernelGGL((k_decode<K_, KI, F, LL, false>), grid, block, 0, st, q, cfg->precision, \
                        rounds, n, S, bs, total_words, offsets, w, mu, sg, symbols, status,      \
-                       nullptr, (int64_t)0)
+                       dev_status, nullptr, (int64_t)0)
     switch (L) {
       case 1: FG_DEC(1); break;
       case 2: FG_DEC(2); break;
@@ -488,7 +481,7 @@ int gmm_encode(const gmm_cfg* cfg, int64_t n, const int32_t* symbols, const floa
   }
   const bool fast = fgmm::use_fast_recip(st);
   int r = fgmm::encode_launch(cfg, n, symbols, w, mu, sg, bitstream, capacity_words, offsets,
-                              wsp, fast, st, nullptr, 0);
+                              wsp, fast, st, nullptr, 0, dev_status);
   if (r == GMM_OK) r = fgmm::finish((uint32_t*)wsp, dev_status, st);
   if (own) (void)hipFreeAsync(wsp, st);
   return r;
@@ -520,10 +513,11 @@ int gmm_decode(const gmm_cfg* cfg, int64_t n, const uint16_t* bitstream, int64_t
   int r;
   if (bracket) {
     r = fgmm::decode_bracket_launch(cfg, n, bitstream, total_words, offsets, w, mu, sg, symbols,
-                                    bracket, stats, (uint32_t*)wsp, fast, st, g_lanes_override);
+                                    bracket, stats, (uint32_t*)wsp, fast, st, g_lanes_override,
+                                    dev_status);
   } else {
     r = fgmm::decode_launch(cfg, n, bitstream, total_words, offsets, w, mu, sg, symbols,
-                            (uint32_t*)wsp, fast, st, g_lanes_override, nullptr, 0);
+                            (uint32_t*)wsp, fast, st, g_lanes_override, nullptr, 0, dev_status);
   }
   if (r == GMM_OK) r = fgmm::finish((uint32_t*)wsp, dev_status, st);
   if (own) (void)hipFreeAsync(wsp, st);
@@ -553,7 +547,7 @@ int gmm_encode_subset(const gmm_cfg* cfg, int64_t n_total, const int32_t* idx, i
   }
   const bool fast = fgmm::use_fast_recip(st);
   int r = fgmm::encode_launch(cfg, m, symbols, w, mu, sg, bitstream, capacity_words, offsets,
-                              wsp, fast, st, idx, n_total);
+                              wsp, fast, st, idx, n_total, dev_status);
   if (r == GMM_OK) r = fgmm::finish((uint32_t*)wsp, dev_status, st);
   if (own) (void)hipFreeAsync(wsp, st);
   return r;
@@ -581,7 +575,8 @@ int gmm_decode_subset(const gmm_cfg* cfg, int64_t n_total, const int32_t* idx, i
   }
   const bool fast = fgmm::use_fast_recip(st);
   int r = fgmm::decode_launch(cfg, m, bitstream, total_words, offsets, w, mu, sg, symbols,
-                              (uint32_t*)wsp, fast, st, g_lanes_override, idx, n_total);
+                              (uint32_t*)wsp, fast, st, g_lanes_override, idx, n_total,
+                              dev_status);
   if (r == GMM_OK) r = fgmm::finish((uint32_t*)wsp, dev_status, st);
   if (own) (void)hipFreeAsync(wsp, st);
   return r;

@@ -19,18 +19,20 @@ int64_t encode_ws_bytes(int64_t n, int64_t S);
 int encode_launch(const gmm_cfg* cfg, int64_t n, const int32_t* symbols, const float* w,
                   const float* mu, const float* sg, uint16_t* bitstream, int64_t capacity,
                   int64_t* offsets, char* ws, bool fast, hipStream_t st,
-                  const int32_t* idx = nullptr, int64_t n_total = 0);
+                  const int32_t* idx = nullptr, int64_t n_total = 0,
+                  int32_t* dev_status = nullptr);
 int decode_launch(const gmm_cfg* cfg, int64_t n, const uint16_t* bs, int64_t total_words,
                   const int64_t* offsets, const float* w, const float* mu, const float* sg,
                   int32_t* symbols, uint32_t* status, bool fast, hipStream_t st, int lanes,
-                  const int32_t* idx = nullptr, int64_t n_total = 0);
+                  const int32_t* idx = nullptr, int64_t n_total = 0,
+                  int32_t* dev_status = nullptr);
 int search_rounds_lps(int32_t N, int L);
 int default_lanes_per_stream(int64_t S);
 int decode_bracket_launch(const gmm_cfg* cfg, int64_t n, const uint16_t* bs, int64_t total_words,
                           const int64_t* offsets, const float* w, const float* mu,
                           const float* sg, int32_t* symbols, const gmm_bracket* bracket,
                           gmm_decode_stats* stats, uint32_t* status, bool fast, hipStream_t st,
-                          int lanes);
+                          int lanes, int32_t* dev_status);
 
 // Launchers of the Polya (kind 2) and binary64-reference (kind 3) CDF
 // kernels (gmm_ablation.hip); launch errors are left for hipGetLastError.
@@ -45,7 +47,7 @@ void ablation_enc_cdf(const QCfg& q, int K, int kind, int64_t n, const int32_t* 
 void ablation_decode(const QCfg& q, int K, int kind, int P, int rounds, int L, int64_t n,
                      int64_t S, const uint16_t* bs, int64_t total_words, const int64_t* offsets,
                      const float* w, const float* mu, const float* sg, int32_t* sym,
-                     uint32_t* status, hipStream_t st);
+                     uint32_t* status, int32_t* dev_status, hipStream_t st);
 
 // Calls fn(integral_constant<K>, integral_constant<kind>, bool_constant<fast>)
 // for the runtime (K, kind, fast) (the logistic kind has no division to

@@ -66,22 +66,28 @@ __global__ void k_enc_cdf(fgmm::QCfg q, int64_t n, const int32_t* __restrict__ s
 }
 
 // Decode with L lanes per stream (L = 1: one lane per stream and a binary
-// search; L > 1: an (L+1)-ary search, ceil(log_{L+1} N) rounds).
+// search; L > 1: an (L+1)-ary search, ceil(log_{L+1} N) rounds). status[0]
+// collects the status bits, status[1] counts finished workgroups (both
+// zeroed before the launch); the last workgroup writes the call's status
+// code to dev_status when given.
 template <int K, int kKind, bool kFast, int L, bool kGather = false>
 __global__ void __launch_bounds__(256)
     k_decode(fgmm::QCfg q, int P, int rounds, int64_t n, int64_t S, const uint16_t* __restrict__ bs,
              int64_t total_words, const int64_t* __restrict__ offsets,
              const float* __restrict__ w, const float* __restrict__ mu,
              const float* __restrict__ sg, int32_t* __restrict__ sym, uint32_t* status,
-             const int32_t* __restrict__ idx = nullptr, int64_t n_total = 0) {
+             int32_t* dev_status, const int32_t* __restrict__ idx = nullptr,
+             int64_t n_total = 0) {
   using namespace fgmm;
   const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t s = gt / L;
   const int g = (int)(gt % L);
   // groups never straddle the S boundary (S * L lanes, L divides 64)
-  if (s >= S) return;
-  const bool bad = decode_stream<K, kKind, kFast, L, kGather>(
-      q, P, rounds, n, S, s, g, bs, total_words, offsets, w, mu, sg, sym, idx, n_total);
-  if (bad && g == 0) atomicOr(status, kStCorrupt);
+  if (s < S) {
+    const bool bad = decode_stream<K, kKind, kFast, L, kGather>(
+        q, P, rounds, n, S, s, g, bs, total_words, offsets, w, mu, sg, sym, idx, n_total);
+    if (bad && g == 0) atomicOr(status, kStCorrupt);
+  }
+  grid_finish_status(status, dev_status);
 }
 

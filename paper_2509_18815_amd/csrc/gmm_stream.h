@@ -9,6 +9,7 @@
 // state map of FlashGMM Eq. (3) x <- (x div f) 2^P + (x mod f) + c; its
 // segment is [x & 0xFFFF, x >> 16, words in the order the decoder reads].
 #pragma once
+#include "../../include/flashgmm.h"
 #include "gmm_device.h"
 
 namespace fgmm {
@@ -227,19 +228,25 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t len, uint32_t* tota
   return base + incl - len;
 }
 
-// Exclusive scan of nblk int64 block totals in one workgroup of 1024
-// threads, tile by tile with a running carry.
+// Exclusive scan of nblk int64 block totals by one workgroup of kBlock
+// threads, tile by tile with a running carry; returns the sum (every
+// thread). Every thread of the workgroup must call it. With kAtomic the
+// totals are read with device-scope atomics (written by other workgroups of
+// the same launch with atomics).
 constexpr int kScanBlock = 1024;
-__device__ __forceinline__ void scan_totals(int64_t nblk, const int64_t* __restrict__ tot,
-                                            int64_t* __restrict__ pre) {
-  __shared__ int64_t wsum[kScanBlock / 64];
+template <int kBlock = kScanBlock, bool kAtomic = false>
+__device__ __forceinline__ int64_t scan_totals(int64_t nblk, const int64_t* __restrict__ tot,
+                                               int64_t* __restrict__ pre) {
+  __shared__ int64_t wsum[kBlock / 64];
   __shared__ int64_t carry_sh;
   if (threadIdx.x == 0) carry_sh = 0;
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int64_t base = 0; base < nblk; base += kScanBlock) {
+  for (int64_t base = 0; base < nblk; base += kBlock) {
     const int64_t i = base + threadIdx.x;
-    const int64_t v = (i < nblk) ? tot[i] : 0;
+    int64_t v = 0;
+    if (i < nblk)
+      v = kAtomic ? (int64_t)atomicAdd((unsigned long long*)(tot + i), 0ull) : tot[i];
     int64_t incl = v;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
@@ -252,9 +259,48 @@ __device__ __forceinline__ void scan_totals(int64_t nblk, const int64_t* __restr
     for (int k = 0; k < wv; ++k) off += wsum[k];
     if (i < nblk) pre[i] = off + incl - v;
     __syncthreads();
-    if (threadIdx.x == kScanBlock - 1) carry_sh = off + incl;
+    if (threadIdx.x == kBlock - 1) carry_sh = off + incl;
     __syncthreads();
   }
+  return carry_sh;
+}
+
+// Status code of a call from its status bits (first match wins).
+__device__ __forceinline__ int32_t status_code(uint32_t b) {
+  if (b & kStInval) return GMM_EINVAL;
+  if (b & kStRange) return GMM_ERANGE;
+  if (b & kStNoSpace) return GMM_ENOSPC;
+  if (b & kStCorrupt) return GMM_ECORRUPT;
+  return GMM_OK;
+}
+
+// True in every thread of the workgroup that finishes last among the
+// grid's workgroups (all threads call it once, at the end). The counter is
+// zeroed before the launch. Data that the last workgroup reads from the
+// others must be written and read with device-scope atomics (performed at
+// the point of coherence of all XCDs): each thread waits for its own memory
+// operations to complete before the workgroup counts itself, so every such
+// atomic precedes the increment that lets the last workgroup through. (A
+// release fence would write back the XCD's whole L2 in every workgroup.)
+__device__ __forceinline__ bool grid_last_block(uint32_t* counter) {
+  __shared__ uint32_t last_sh;
+  __builtin_amdgcn_s_waitcnt(kWaitVm0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t total = gridDim.x * gridDim.y * gridDim.z;
+    last_sh = (atomicAdd(counter, 1u) == total - 1u) ? 1u : 0u;
+  }
+  __syncthreads();
+  return last_sh != 0u;
+}
+
+// The last workgroup of a launch writes the call's status code from the
+// status bits (bits[0]; bits[1] is the workgroup counter) to dev_status,
+// when given. All threads call it once, at the end of the kernel.
+__device__ __forceinline__ void grid_finish_status(uint32_t* bits, int32_t* dev_status) {
+  if (dev_status == nullptr) return;
+  if (grid_last_block(bits + 1) && threadIdx.x == 0)
+    *dev_status = status_code(atomicOr(bits, 0u));
 }
 
 // Copies stream segment [x lo, x hi, cnt words] to dst with `lanes` lanes
