@@ -317,7 +317,9 @@ __device__ __forceinline__ uint32_t cdf_inner(const Elem<K>& e, const QCfg& q, i
     const float z = (b - e.mu[k]) * e.r[k];
     F = fma32(e.w[k], phi_tilde<kKind, kFastRecip>(z), F);
   }
-  F = __builtin_fminf(F, 1.0f);
+  // min(F, 1): F >= 0, so clamping to [0, 1] is the same value, and the
+  // clamp folds into the last fused multiply-add as its output modifier
+  F = __builtin_fminf(__builtin_fmaxf(F, 0.0f), 1.0f);
   // F >= 0 (w' >= 0 and Phi~ >= 0), so the truncating conversion is the floor
   return (uint32_t)j + (uint32_t)(F * q.span);
 }

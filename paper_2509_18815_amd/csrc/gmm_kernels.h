@@ -44,7 +44,7 @@ __global__ void k_inverse(fgmm::QCfg q, int rounds, int64_t n, const float* __re
     s = q.M - 1;
   }
   uint32_t cl, ch;
-  jout[i] = search_bs<K, kKind, kFast>(e, q, rounds, s, cl, ch);
+  jout[i] = search_bs<K, kKind, kFast>(e, q, rounds, free_rounds(rounds, q.N), s, cl, ch);
 }
 
 // Encode phase 1: one thread per element (per pass position with kGather:

@@ -34,13 +34,37 @@ __device__ __forceinline__ int64_t gather_index(const int32_t* __restrict__ idx,
 // the round testing lo + h, c_lo = c(lo) <= slot < c_hi = c(lo + 2h), so
 // on return c_lo = c_j and c_hi = c_{j+1}; since slot < M, lo never reaches
 // N.
+//
+// A midpoint lo + h is at most 2^rounds - h, so only the rounds with
+// h <= 2^rounds - N can test an index >= N (for N = 2^rounds - 1 only the
+// last one); the others skip that select (a wavefront-uniform branch).
+//
+// Leading rounds whose midpoints stay below N: those with 2^r > 2^rounds - N.
+__device__ __forceinline__ int free_rounds(int rounds, int32_t N) {
+  const int32_t pad = (1 << rounds) - N;
+  int nfree = 0;
+  while (nfree < rounds && (1 << (rounds - 1 - nfree)) > pad) ++nfree;
+  return nfree;
+}
+
+// nfree = free_rounds(rounds, N), computed once by the caller.
 template <int K, int kKind, bool kFast>
 __device__ __forceinline__ int32_t search_bs(const Elem<K>& e, const QCfg& q, int rounds,
-                                             uint32_t slot, uint32_t& c_lo, uint32_t& c_hi) {
+                                             int nfree, uint32_t slot, uint32_t& c_lo,
+                                             uint32_t& c_hi) {
   int32_t lo = 0;
   c_lo = 0;
   c_hi = q.M;
-  for (int r = rounds - 1; r >= 0; --r) {
+  int r = rounds - 1;
+  for (int i = 0; i < nfree; ++i, --r) {
+    const int32_t mid = lo + (1 << r);
+    const uint32_t c = cdf_inner<K, kKind, kFast>(e, q, mid);
+    const bool right = slot >= c;
+    lo = right ? mid : lo;
+    c_lo = right ? c : c_lo;
+    c_hi = right ? c_hi : c;
+  }
+  for (; r >= 0; --r) {
     const int32_t mid = lo + (1 << r);
     const uint32_t c = cdf_upper<K, kKind, kFast>(e, q, mid);
     const bool right = slot >= c;
@@ -362,6 +386,7 @@ __device__ __forceinline__ bool decode_stream(const QCfg& q, int P, int rounds, 
   bool bad = x < (1u << 16);
   const uint32_t mask = q.M - 1;
   if (ns == 0) return bad || x != (1u << 16) || ptr != b;
+  const int nfree = (L == 1) ? free_rounds(rounds, q.N) : 0;
   // Software pipeline over the stream's steps. Each step issues, after its
   // own refill, first the bitstream word the next step's refill may need and
   // then the parameters of the element kRing steps ahead into a ring of
@@ -401,7 +426,7 @@ __device__ __forceinline__ bool decode_stream(const QCfg& q, int P, int rounds, 
         const Elem<K> e = make_elem<K, kFast, kKind>(q, cw, cm, cs);
         int32_t j;
         if (L == 1)
-          j = search_bs<K, kKind, kFast>(e, q, rounds, slot, cl, ch);
+          j = search_bs<K, kKind, kFast>(e, q, rounds, nfree, slot, cl, ch);
         else
           j = search_group<K, kKind, kFast, L>(e, q, rounds, slot, g, gbase, gmask, 0, q.N, cl,
                                                ch);
