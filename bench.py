@@ -26,6 +26,8 @@ if ROOT not in sys.path:
 # HBM3E peak and FP32 vector peak of one MI355X (AMD public figures).
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
+# Non-packed FP32 VALU issue rate: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz.
+VALU_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9
 
 
 def flops_per_eval(K: int) -> int:
@@ -188,7 +190,7 @@ def traffic_record(root: str, kernel: str, grid: int) -> dict:
     import glob
 
     ctr = collections.defaultdict(list)
-    for sub in ("fetch", "write"):
+    for sub in ("fetch", "write", "valu"):
         for f in glob.glob(os.path.join(root, sub, "*counter_collection.csv")):
             for r in csv.DictReader(open(f)):
                 ctr[(r["Kernel_Name"].replace("void ", "").split("(")[0], int(r["Grid_Size"]),
@@ -200,9 +202,14 @@ def traffic_record(root: str, kernel: str, grid: int) -> dict:
     ff = float(1 << 20) / mean(ctr[(cal[0], cal[1], "FETCH_SIZE")])
     rd = mean(ctr[(kernel, grid, "FETCH_SIZE")]) * ff * 1024
     wr = mean(ctr[(kernel, grid, "WRITE_SIZE")]) * wf * 1024
-    return {"kernel": kernel, "grid": grid, "read_bytes": rd, "write_bytes": wr,
-            "traffic_bytes": rd + wr, "fetch_scale": ff, "write_scale": wf,
-            "source_sha": kernel_source_hash()}
+    rec = {"kernel": kernel, "grid": grid, "read_bytes": rd, "write_bytes": wr,
+           "traffic_bytes": rd + wr, "fetch_scale": ff, "write_scale": wf,
+           "source_sha": kernel_source_hash()}
+    vi = ctr.get((kernel, grid, "SQ_INSTS_VALU"))
+    if vi:
+        # wavefront VALU instructions per launch (each covers 64 lanes)
+        rec["valu_wave_instructions"] = mean(vi)
+    return rec
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_decode_4k_320x135x240_traffic.json")
@@ -593,17 +600,36 @@ def main():
     dec_t = dec_in_steps
     achieved = decode_flops_per_symbol(K, N) * big.n / dec_t / 1e12
     traffic = None
+    counters = None
     if os.path.exists(TRAFFIC_FILE):
         rec = json.load(open(TRAFFIC_FILE))
         if rec.get("source_sha") == kernel_source_hash():
             traffic = rec["traffic_bytes"]
+            # counter-derived rates at this run's in-step launch time: HBM
+            # bytes against 8 TB/s, and VALU lane-instructions (64 per
+            # wavefront instruction) against the issue rate of non-packed
+            # FP32 instructions, 256 CU x 4 SIMD x 16 lanes x 2.4 GHz (packed
+            # FP32 is not generated by this build; the 157.3 TFLOP/s peak
+            # counts packed FMA as 4 flops per lane)
+            counters = {"source": os.path.relpath(TRAFFIC_FILE, ROOT),
+                        "hbm_GBps": round(traffic / dec_t / 1e9, 1),
+                        "hbm_frac": round(traffic / dec_t / 1e9 / PEAK_HBM_GBS, 4)}
+            if "valu_wave_instructions" in rec:
+                lane_ops = rec["valu_wave_instructions"] * 64 / dec_t
+                counters.update({
+                    "valu_instructions_per_symbol": round(
+                        rec["valu_wave_instructions"] * 64 / big.n, 1),
+                    "valu_lane_instr_per_s": float("%.4g" % lane_ops),
+                    "valu_issue_peak_lane_instr_per_s": VALU_ISSUE_PEAK,
+                    "valu_issue_frac": round(lane_ops / VALU_ISSUE_PEAK, 4)})
     roofline = {"bound": "alu", "kernel": "k_decode (4K latent, 65,536 streams)",
                 "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
                 "flops_per_symbol": decode_flops_per_symbol(K, N),
                 "symbols_per_launch": big.n,
                 "launch_ms": round(dec_t * 1e3, 4),
-                "launch_ms_isolated": round(ev[("c2b", "decode")] * 1e3, 4)}
+                "launch_ms_isolated": round(ev[("c2b", "decode")] * 1e3, 4),
+                "counters": counters}
     out = {
         "metric": "GMM rANS decode+encode symbols/s, bit-exact; plain vs batched+learned bracket",
         "value": value, "unit": "symbols/s", "n_gpus": 1, "steps": args.steps,
