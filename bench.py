@@ -2,9 +2,12 @@
 
 A step codes the paper-scale workload once: the Kodak-size latent
 (320x48x32, 4,096 streams) and the 4K latent (320x135x240, 65,536 streams),
-K = 3, support [-255, 255], P = 16 — encode both, then decode both. Inputs
-are seeded synthetic latents resident in HBM before timing starts; every
-timed step's output is the bit-exact round trip (checked after timing).
+K = 3, support [-255, 255], P = 16 — each latent encoded, then decoded. The
+two latents are independent, so their chains run on two HIP streams (both
+at the default priority): the Kodak-size latent's latency-bound kernels
+fill issue slots that the 4K latent's kernels leave free. Inputs are
+seeded synthetic latents resident in HBM before timing starts; every timed
+step's output is the bit-exact round trip (checked after timing).
 
 value = symbols coded per second, each symbol encoded and decoded once per
 step: (n_kodak + n_4k) * steps / elapsed.
@@ -537,15 +540,20 @@ def main():
         lats[nm] = Latent(api, cfgd, lat)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
+    side = torch.cuda.Stream()  # default priority
 
     # HIP events around the 4K-latent decode (the dominant kernel) on the
     # launch stream, recorded inside the timed steps
     ev_pairs = []
 
     def step(record=False):
-        for nm in names:
-            lats[nm].encode()
-        lats["c2a"].decode()
+        # the Kodak-size latent's chain on the side stream, the 4K latent's
+        # on the main stream; the step ends when both have finished
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            lats["c2a"].encode()
+            lats["c2a"].decode()
+        lats["c2b"].encode()
         if record:
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)
@@ -555,6 +563,7 @@ def main():
             ev_pairs.append((a, b))
         else:
             lats["c2b"].decode()
+        stream.wait_stream(side)
 
     for _ in range(args.warmup):
         step()
@@ -629,6 +638,10 @@ def main():
                 "symbols_per_launch": big.n,
                 "launch_ms": round(dec_t * 1e3, 4),
                 "launch_ms_isolated": round(ev[("c2b", "decode")] * 1e3, 4),
+                # the same launch back to back on its own (no co-running
+                # Kodak-latent kernels), for comparison
+                "achieved_isolated": round(decode_flops_per_symbol(K, N) * big.n
+                                           / ev[("c2b", "decode")] / 1e12, 3),
                 "counters": counters}
     out = {
         "metric": "GMM rANS decode+encode symbols/s, bit-exact; plain vs batched+learned bracket",
@@ -637,7 +650,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "plain method at paper scale: 320x48x32 (4,096 streams) + "
-                               "320x135x240 (65,536 streams), K=3, support [-255,255], P=16",
+                               "320x135x240 (65,536 streams), K=3, support [-255,255], P=16; "
+                               "one HIP stream per latent",
                    "symbols_per_step": n_total},
         "roofline": roofline,
         "forms": forms,
