@@ -8,12 +8,15 @@
 //   k_enc_rans  one lane per stream: the integer rANS recurrence of Eq. (3)
 //               in reverse element order, renormalisation words written to
 //               the stream's scratch region in decoder order, then a
-//               wavefront/block prefix sum of the segment lengths;
-//   k_scan_blk  prefix sum of the per-block segment totals;
+//               wavefront/block prefix sum of the segment lengths; the
+//               workgroup that finishes last scans the block totals and
+//               writes the call's status;
 //   k_pack      stream offsets and the compacted bitstream.
 // Decode (Sec. III-A: binary search over the monotone CDF) runs one lane per
-// stream with a branch-uniform search: every lane executes exactly
-// ceil(log2 N) CDF evaluations per symbol, with no early exit.
+// stream with a branch-uniform search (every lane executes exactly
+// ceil(log2 N) CDF evaluations per symbol, with no early exit), or L lanes
+// per stream with an (L+1)-ary search when streams are few; its last
+// workgroup writes the call's status.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
