@@ -400,6 +400,42 @@ def bracket_few_streams_form(api, synth, dev, name, model, reps=10):
             "wave_all_hit": all_hit / max(steps, 1)}
 
 
+def learned_step_form(api, lats, model, step, steps, warmup, plain_value, dev):
+    """The timed step of the headline measurement again, with the
+    Kodak-size latent decoded through the learned bracket's group form (the
+    network on the matrix cores, one 16-boundary window round) while the 4K
+    latent's decode runs beside it: the two decodes share the SIMDs, and the
+    bracket moves most of the Kodak-latent decode off the vector ALUs that
+    bound the 4K decode. Same bitstreams, outputs verified."""
+    import torch
+    L = lats["c2a"]
+    br = model.load()
+    stats = torch.zeros(4, dtype=torch.int64, device=dev)
+
+    def kodak_decode():
+        r = api.decode_into(L.cfg, L.bs, L.off, L.lat.weights, L.lat.means, L.lat.scales, L.dec,
+                            bracket=br, stats=stats, ws=L.ws_dec, status=L.st[1:2])
+        assert r == 0
+    for _ in range(warmup):
+        step(kodak_decode=kodak_decode)
+    torch.cuda.synchronize()
+    stats.zero_()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(kodak_decode=kodak_decode)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    for nm in lats:
+        lats[nm].verify()
+    hits, misses, _, _ = stats.cpu().tolist()
+    br.close()
+    n_total = sum(lats[nm].n for nm in lats)
+    v = n_total * steps / elapsed
+    return {"value": v, "unit": "symbols/s", "ms_per_step": elapsed / steps * 1e3,
+            "gain_vs_plain_step": v / plain_value,
+            "kodak_latent_hit_rate": hits / max(hits + misses, 1)}
+
+
 # The paper's Table II (CPU, per 768x512 Kodak image; encode / decode ms),
 # quoted as context for the same comparison on one MI355X.
 PAPER_TABLE2_MS = {"no_approximation": (56.5, 127.0), "polya": (23.5, 34.3),
@@ -546,13 +582,13 @@ def main():
     # launch stream, recorded inside the timed steps
     ev_pairs = []
 
-    def step(record=False):
+    def step(record=False, kodak_decode=None):
         # the Kodak-size latent's chain on the side stream, the 4K latent's
         # on the main stream; the step ends when both have finished
         side.wait_stream(stream)
         with torch.cuda.stream(side):
             lats["c2a"].encode()
-            lats["c2a"].decode()
+            (kodak_decode or lats["c2a"].decode)()
         lats["c2b"].encode()
         if record:
             a = torch.cuda.Event(enable_timing=True)
@@ -669,6 +705,8 @@ def main():
         # the same model (same parameter distributions and support) on the
         # Kodak-size latent, whose 4,096 streams decode with 16 lanes each
         forms["c2a_bracket"] = bracket_few_streams_form(api, synth, dev, "c2a", m4)
+        forms["step_learned_bracket"] = learned_step_form(api, lats, m4, step, args.steps,
+                                                          args.warmup, value, dev)
         c1 = synth.CONFIGS["c1"]
         m1 = train.train_bracket(c1.K, c1.lo, c1.hi, c1.precision, n_train=args.bracket_tuples,
                                  seed=synth.TRAIN_SEED_C1, device=dev)

@@ -315,10 +315,11 @@ int gmm_plan_destroy(gmm_plan* plan);
  * evaluations (for latents with few streams); 0 (default) chooses from the
  * stream count: the smallest power of two up to 32 that gives at least
  * 65,536 lanes. With a bracket, 16 or more lanes select the group form
- * (16 lanes per stream: the network's prediction seeds one round that
+ * with 16 lanes per stream (the network's prediction seeds one round that
  * evaluates 16 consecutive boundaries, with a 17-ary search as fallback),
- * fewer the one-lane form (a verified bracket of radius R, then a binary
- * search). Output is identical for every choice. GMM_EINVAL otherwise. */
+ * 8 lanes the group form with 8 (8 boundaries, 9-ary fallback), fewer the
+ * one-lane form (a verified bracket of radius R, then a binary search).
+ * Output is identical for every choice. GMM_EINVAL otherwise. */
 int gmm_set_decode_lanes(int32_t lanes);
 
 /* Diagnostic: number of floats u in [2^-10, 2^10] on which the coder's fused

@@ -68,8 +68,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
   grid_finish_status(status, dev_status);
 }
 
-// Group form: 16 lanes per stream, four streams per wavefront.
-template <int K, int kKind, bool kFast>
+// Group form: LG = 16 or 8 lanes per stream, 64 / LG streams per wavefront.
+template <int K, int kKind, bool kFast, int LG>
 __global__ void __launch_bounds__(256)
     k_decode_bracket_group(QCfg q, int P, int64_t n, int64_t S, const uint16_t* __restrict__ bs,
                            int64_t total_words, const int64_t* __restrict__ offsets,
@@ -77,13 +77,13 @@ __global__ void __launch_bounds__(256)
                            const float* __restrict__ sg, int32_t* __restrict__ sym,
                            uint32_t* status, const BracketDev* __restrict__ br,
                            unsigned long long* stats, int32_t* dev_status) {
-  const int64_t s0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64 * 4;
+  const int64_t s0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64 * (64 / LG);
   if (s0 < S) {  // whole wavefronts
     GroupModel gm;
     load_group_model(br, gm);
     unsigned long long cnt[4] = {0, 0, 0, 0};
-    bracket_group_decode<K, kKind, kFast>(q, P, n, S, s0, bs, total_words, offsets, w, mu, sg,
-                                          sym, status, br, gm, cnt);
+    bracket_group_decode<K, kKind, kFast, LG>(q, P, n, S, s0, bs, total_words, offsets, w, mu,
+                                              sg, sym, status, br, gm, cnt);
     bracket_flush_stats(cnt, stats);
   }
   grid_finish_status(status, dev_status);
@@ -134,8 +134,15 @@ int decode_bracket_launch(const gmm_cfg* cfg, int64_t n, const uint16_t* bs, int
     constexpr int K_ = decltype(Kc)::value;
     if constexpr (K_ <= 5) {
       if (L >= 16)
-        hipLaunchKernelGGL((k_decode_bracket_group<K_, decltype(kc)::value, decltype(fc)::value>),
+        hipLaunchKernelGGL((k_decode_bracket_group<K_, decltype(kc)::value, decltype(fc)::value,
+                                                   16>),
                            dim3((unsigned)((S + 15) / 16)), dim3(256), 0, st, q, cfg->precision,
+                           n, S, bs, total_words, offsets, w, mu, sg, symbols, status, br->dev,
+                           (unsigned long long*)stats, dev_status);
+      else if (L == 8)
+        hipLaunchKernelGGL((k_decode_bracket_group<K_, decltype(kc)::value, decltype(fc)::value,
+                                                   8>),
+                           dim3((unsigned)((S + 31) / 32)), dim3(256), 0, st, q, cfg->precision,
                            n, S, bs, total_words, offsets, w, mu, sg, symbols, status, br->dev,
                            (unsigned long long*)stats, dev_status);
       else

@@ -427,15 +427,18 @@ __device__ __forceinline__ bf16x8 relu_operand(const f32x4& lo, const f32x4& hi)
   return __builtin_bit_cast(bf16x8, v);
 }
 
-// B operand of layer 1 (inputs as rows, samples as columns): lane l feeds
-// column c = l % 16 with inputs 8 (l / 16) .. 8 (l / 16) + 7. Column c < 4
-// is the sample of lane group c, whose lanes all hold its inputs x; lanes
-// 8..15 of a group serve inputs 8..15, lanes 0..7 inputs 0..7. Input 16 is
-// the constant 1 of the folded bias; columns 4..15 carry copies and are not
+// B operand of layer 1 (inputs as rows, samples as columns) for groups of
+// LG lanes (64 / LG streams per wavefront): lane l feeds column c = l % 16
+// with inputs 8 (l / 16) .. 8 (l / 16) + 7. Column c < 64 / LG is the sample
+// of lane group c, whose lanes all hold its inputs x; the upper half of a
+// group serves inputs 8..15, the lower half inputs 0..7. Input 16 is the
+// constant 1 of the folded bias; the other columns carry copies and are not
 // read.
+template <int LG>
 __device__ __forceinline__ bf16x8 group_operand(const float (&x)[16]) {
+  constexpr int G = 64 / LG;  // streams per wavefront
   const int l = threadIdx.x & 63;
-  const bool upper = (l & 15) >= 8;
+  const bool upper = (l % LG) >= LG / 2;
   uint32_t wv[4];
 #pragma unroll
   for (int w = 0; w < 4; ++w) {
@@ -445,7 +448,7 @@ __device__ __forceinline__ bf16x8 group_operand(const float (&x)[16]) {
     wv[w] = upper ? hi : lo;
   }
   const int kh = l >> 4;
-  const int src = 16 * (l & 3) + 8 * (kh & 1);
+  const int src = LG * ((l & 15) % G) + (LG / 2) * (kh & 1);
   u32x4 rv;
 #pragma unroll
   for (int w = 0; w < 4; ++w) rv[w] = __shfl(wv[w], src, 64);
@@ -482,25 +485,26 @@ __device__ __forceinline__ float mlp_group(const BracketDev* __restrict__ br, co
   return fmaf(acc3[0] + br->b3, br->out_std, br->out_mean);
 }
 
-// Decodes streams s0 .. s0+3 of one latent, 16 lanes each (lane group
-// l / 16 takes stream s0 + l / 16). Every lane runs every step of the
+// Decodes streams s0 .. s0 + 64/LG - 1 of one latent, LG = 16 or 8 lanes
+// each (lane group l / LG takes stream s0 + l / LG); the window holds LG
+// boundaries around the prediction. Every lane runs every step of the
 // wavefront's longest stream (finished groups compute on placeholder data
 // and store nothing): the matrix-core inference needs all 64 lanes.
 // Counters (lane 0 of each group): hit / miss symbols; lane 0 of the
 // wavefront also counts wavefront steps and steps on which every active
 // stream hit.
-template <int K, int kKind, bool kFast>
+template <int K, int kKind, bool kFast, int LG>
 __device__ __forceinline__ void bracket_group_decode(
     const QCfg& q, int P, int64_t n, int64_t S, int64_t s0, const uint16_t* __restrict__ bs,
     int64_t total_words, const int64_t* __restrict__ offsets, const float* __restrict__ w,
     const float* __restrict__ mu, const float* __restrict__ sg, int32_t* __restrict__ sym,
     uint32_t* status, const BracketDev* __restrict__ br, const GroupModel& gm,
     unsigned long long (&cnt)[4]) {
-  constexpr int L = 16;
-  constexpr int kHalf = 7;  // window [p - 7, p + 8]: 16 boundaries, 15 symbols
+  constexpr int L = LG;
+  constexpr int kHalf = LG / 2 - 1;  // window [p - kHalf, p + kHalf + 1]: LG boundaries
   const int l = threadIdx.x & 63;
-  const int gi = l >> 4, g = l & 15, gbase = l & 48;
-  const uint64_t gmask = 0xFFFFull << gbase;
+  const int gi = l / L, g = l % L, gbase = gi * L;
+  const uint64_t gmask = ((1ull << L) - 1ull) << gbase;
   const int64_t s = s0 + gi;
   const int64_t ns_max = stream_len(n, S, s0);  // lower-index streams are never shorter
   const int64_t ns = (s < S) ? stream_len(n, S, s) : 0;
@@ -563,7 +567,7 @@ __device__ __forceinline__ void bracket_group_decode(
         feat[2 * K + k] = __builtin_amdgcn_logf(e.r[k]);  // log2(1 / scale')
       }
       feat[3 * K] = (float)slot * inv_m;
-      const float pred_col = mlp_group(br, gm, group_operand(feat));
+      const float pred_col = mlp_group(br, gm, group_operand<LG>(feat));
       const float pred = __shfl(pred_col, gi, 64);  // column gi = this group's sample
       // window of 16 boundaries around the prediction, inside the indices
       // [slot - (M - N), slot] that the quantization allows for this slot

@@ -185,10 +185,11 @@ def lanes(api, request):
     api.set_decode_lanes(0)
 
 
-@pytest.mark.parametrize("lanes", [0, 1, 16], indirect=True)
+@pytest.mark.parametrize("lanes", [0, 1, 8, 16], indirect=True)
 def test_bracket_decode_matches_oracle_on_corruption(api, orc, trained, lanes):
     """333 streams: the group form (16 lanes per stream, partial last
-    wavefront) by default and with 16 lanes, the one-lane form with 1."""
+    wavefront) by default and with 16 lanes, with 8 lanes per stream with
+    8, the one-lane form with 1."""
     br = trained.load()
     rng = np.random.default_rng(11)
     n, K, S = 20000, 3, 333
@@ -211,7 +212,8 @@ def test_bracket_decode_matches_oracle_on_corruption(api, orc, trained, lanes):
     br.close()
 
 
-def test_group_bracket_decode_kodak_latent(api, orc, trained):
+@pytest.mark.parametrize("lanes", [0, 8], indirect=True)
+def test_group_bracket_decode_kodak_latent(api, orc, trained, lanes):
     """The 320x48x32 latent at 4,096 streams decodes with 16 lanes per stream:
     the group form of the bracket (matrix-core inference for four streams
     per wavefront, one 16-boundary window round) is bit-identical to the
@@ -232,7 +234,7 @@ def test_group_bracket_decode_kodak_latent(api, orc, trained):
     assert torch.equal(dec, lat.symbols)
     hits, misses, all_hit, steps = stats.cpu().tolist()
     assert hits + misses == lat.n
-    assert hits / lat.n > 0.97, hits / lat.n
+    assert hits / lat.n > (0.97 if lanes != 8 else 0.93), hits / lat.n
     rng = np.random.default_rng(19)
     bad = api.Bracket(3, rand_net(rng, 10, orc, 1.0), trained.in_mean, trained.in_std, 0.0, 50.0)
     stats.zero_()
@@ -260,7 +262,7 @@ def test_group_bracket_decode_kodak_latent(api, orc, trained):
                                          dec, bracket=br, status=st_d))
     torch.cuda.synchronize()
     assert st_d.item() == 0 and torch.equal(dec, lat.symbols)
-    print(f"group bracket (320x48x32, 4096 streams): hit rate {hits / lat.n:.4f}, all-hit "
+    print(f"group bracket (320x48x32, 4096 streams, lanes {lanes}): hit rate {hits / lat.n:.4f}, all-hit "
           f"wavefront steps {all_hit / steps:.3f}, untrained hit rate {h2 / lat.n:.3f}, "
           f"plain {t_plain:.4f} ms, bracket {t_br:.4f} ms, gain {t_plain / t_br:.3f}x")
     br.close()
