@@ -254,3 +254,51 @@ def test_async_status_and_determinism(api):
         outs.append((u16(bs)[: int(off[-1].item())].copy(), off.cpu().numpy()))
     for o in outs[1:]:
         assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
+
+
+def test_two_streams_concurrent_bit_exact(api, orc):
+    """Two latents coded at once on two HIP streams (each with its own
+    workspace and device status), several rounds back to back with no host
+    synchronisation in between, as the benchmark step runs them: every
+    bitstream, offset table and decoded symbol equals the oracle's, and every
+    status is OK. One latent has few streams (32 lanes per stream in
+    decode), the other 65,536 (one lane per stream)."""
+    rng = np.random.default_rng(21)
+    cases = [(30000, 3, -255, 255, 256), (300000, 3, -255, 255, 65536)]
+    main = torch.cuda.current_stream()
+    side = torch.cuda.Stream()
+    work = []
+    for n, K, lo, hi, S in cases:
+        w, mu, sig = synth.random_params(rng, n, K)
+        sym = np.clip(np.rint(rng.normal(0, 6, size=n)), lo, hi).astype(np.int32)
+        ocfg = orc.make_cfg(K, lo, hi, 16, S)
+        st, obs, ooff = orc.encode(ocfg, sym, w, mu, sig)
+        assert st == orc.OK
+        cfg = api.make_cfg(K, lo, hi, 16, S)
+        t = {"sym": dev(sym), "w": dev(w), "mu": dev(mu), "sig": dev(sig),
+             "bs": torch.empty(n + 2 * S, dtype=torch.int16, device="cuda"),
+             "off": torch.empty(S + 1, dtype=torch.int64, device="cuda"),
+             "dec": torch.empty(n, dtype=torch.int32, device="cuda"),
+             "wse": torch.empty(api.workspace_bytes(cfg, n, 0), dtype=torch.uint8, device="cuda"),
+             "wsd": torch.empty(api.workspace_bytes(cfg, n, 1), dtype=torch.uint8, device="cuda"),
+             "st": torch.full((2,), -1, dtype=torch.int32, device="cuda")}
+        work.append((cfg, t, sym, obs, ooff))
+
+    def chain(cfg, t):
+        assert api.encode_into(cfg, t["sym"], t["w"], t["mu"], t["sig"], t["bs"], t["off"],
+                               ws=t["wse"], status=t["st"][0:1]) == api.OK
+        assert api.decode_into(cfg, t["bs"], t["off"], t["w"], t["mu"], t["sig"], t["dec"],
+                               ws=t["wsd"], status=t["st"][1:2]) == api.OK
+    torch.cuda.synchronize()
+    for _ in range(4):
+        side.wait_stream(main)
+        with torch.cuda.stream(side):
+            chain(*work[0][:2])
+        chain(*work[1][:2])
+        main.wait_stream(side)
+    torch.cuda.synchronize()
+    for cfg, t, sym, obs, ooff in work:
+        assert t["st"].tolist() == [api.OK, api.OK]
+        assert np.array_equal(t["off"].cpu().numpy(), ooff)
+        assert np.array_equal(u16(t["bs"])[: ooff[-1]], obs)
+        assert np.array_equal(t["dec"].cpu().numpy(), sym)
