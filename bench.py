@@ -50,6 +50,22 @@ def encode_flops_per_symbol(K: int) -> int:
     return 2 * flops_per_eval(K) + 4 * K
 
 
+def form_roofline(K: int, N: int, enc_sym_s: float, dec_sym_s: float, bits: float) -> dict:
+    """Algorithmic rates of a form: binary32 flops (the method's, per
+    symbol) and HBM bytes (3K parameter floats and one int32 symbol per
+    symbol, plus the bitstream) times the measured symbol rate, as
+    fractions of the MI355X FP32 vector and HBM peaks."""
+    byt = 12 * K + 4 + bits / 8
+
+    def rates(sym_s, flops):
+        return {"tflops": round(flops * sym_s / 1e12, 2),
+                "frac_fp32": round(flops * sym_s / 1e12 / PEAK_FP32_TFLOPS, 4),
+                "hbm_GBps": round(byt * sym_s / 1e9, 1),
+                "frac_hbm": round(byt * sym_s / 1e9 / PEAK_HBM_GBS, 4)}
+    return {"encode": rates(enc_sym_s, encode_flops_per_symbol(K)),
+            "decode": rates(dec_sym_s, decode_flops_per_symbol(K, N))}
+
+
 class Latent:
     def __init__(self, api, cfgd, lat, cdf_kind=0, param_kind=0):
         import torch
@@ -296,6 +312,8 @@ def batched_form(api, synth, name, dev, reps=5, bracket_model=None, loop_baselin
         out = {"latents": len(lats), "n": n_tot, "K": cfgd.K, "support": [cfgd.lo, cfgd.hi],
                "encode_sym_s": n_tot / t_enc, "decode_sym_s": n_tot / t_dec,
                "roundtrip_sym_s": n_tot / (t_enc + t_dec), "bits_per_symbol": 16.0 * words / n_tot,
+               "roofline": form_roofline(cfgd.K, cfgd.hi - cfgd.lo + 1, n_tot / t_enc,
+                                         n_tot / t_dec, 16.0 * words / n_tot),
                "encode_plan": pe.info(), "decode_plan": pd.info(), "bracket": bracket_out}
         pe.close()
         pd.close()
@@ -323,6 +341,8 @@ def batched_form(api, synth, name, dev, reps=5, bracket_model=None, loop_baselin
            "encode_sym_s": n_tot / t_enc, "decode_sym_s": n_tot / t_dec,
            "roundtrip_sym_s": n_tot / (t_enc + t_dec),
            "bits_per_symbol": 16.0 * words / n_tot,
+           "roofline": form_roofline(cfgd.K, cfgd.hi - cfgd.lo + 1, n_tot / t_enc,
+                                     n_tot / t_dec, 16.0 * words / n_tot),
            "encode_plan": pe.info(), "decode_plan": pd.info(),
            "single_call_loop": {"encode_sym_s": n_tot / t_enc1, "decode_sym_s": n_tot / t_dec1},
            "bracket": bracket_out}
@@ -636,10 +656,14 @@ def main():
     forms = {}
     for nm in names:
         L = lats[nm]
+        bps = 16.0 * float(L.off[-1].item()) / L.n
         forms[nm] = {"shape": list(L.lat.shape), "n": L.n, "streams": L.S,
                      "encode_sym_s": L.n / ev[(nm, "encode")],
                      "decode_sym_s": L.n / ev[(nm, "decode")],
-                     "bits_per_symbol": 16.0 * float(L.off[-1].item()) / L.n}
+                     "bits_per_symbol": bps,
+                     "roofline": form_roofline(L.cfgd.K, L.cfgd.hi - L.cfgd.lo + 1,
+                                               L.n / ev[(nm, "encode")],
+                                               L.n / ev[(nm, "decode")], bps)}
     big = lats["c2b"]
     K, N = big.cfgd.K, big.cfgd.hi - big.cfgd.lo + 1
     dec_t = dec_in_steps
