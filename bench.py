@@ -34,20 +34,25 @@ VALU_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9
 
 
 def flops_per_eval(K: int) -> int:
-    """Algorithmic binary32 flops of one mixture CDF evaluation (fma = 2):
-    per component 45 (z: 2, clamp: 2, u: 2, 1/u: 1, polynomial: 9, a^2 and
-    -a^2/2: 2, exp: 21, C e and tail: 2, cap and reflection: 2, mixture
-    fma: 2) plus 4 per evaluation (boundary, clamp, scale, floor)."""
-    return 45 * K + 4
+    """Algorithmic binary32 flops of one A&S mixture CDF evaluation (fma =
+    2): per component 40 (b - mu: 1, a = min(|d| r/9, 1): 2, u: 2, 1/u: 1,
+    polynomial: 9, a^2: 1, split of the exponent: 5, degree-6 polynomial of
+    the density: 12, 2^n scaling: 1, density times polynomial: 1, 1/2 - T
+    floored at 0: 2, sign: 1, mixture fma: 2) plus 4 per evaluation
+    (boundary, clamp, scale, floor)."""
+    return 40 * K + 4
 
 
 def decode_flops_per_symbol(K: int, N: int) -> int:
+    """ceil(log2 N) evaluations plus the per-element setup, 6 per component
+    (scale clamp: 2, reciprocal: 1, weight flush: 1, r/9: 1, half-weight
+    sum: 1)."""
     rounds = (N - 1).bit_length()
-    return rounds * flops_per_eval(K) + 4 * K
+    return rounds * flops_per_eval(K) + 6 * K
 
 
 def encode_flops_per_symbol(K: int) -> int:
-    return 2 * flops_per_eval(K) + 4 * K
+    return 2 * flops_per_eval(K) + 6 * K
 
 
 def form_roofline(K: int, N: int, enc_sym_s: float, dec_sym_s: float, bits: float) -> dict:

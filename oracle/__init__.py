@@ -57,6 +57,8 @@ def lib():
         sigs = {
             "gmm_oracle_phi": (ctypes.c_float, [ctypes.c_float, i32]),
             "gmm_oracle_exp": (ctypes.c_float, [ctypes.c_float]),
+            "gmm_oracle_as_tail": (ctypes.c_float, [ctypes.c_float]),
+            "gmm_oracle_as_half": (ctypes.c_float, [ctypes.c_float, ctypes.c_float]),
             "gmm_oracle_phi_batch": (None, [P, P, i64, i32]),
             "gmm_oracle_exp_batch": (None, [P, P, i64]),
             "gmm_oracle_F_table": (ctypes.c_int, [cfgp, i64, P, P, P, P]),
@@ -104,6 +106,22 @@ def phi(z, kind=0) -> np.ndarray:
     out = np.empty_like(z)
     lib().gmm_oracle_phi_batch(_p(z), _p(out), z.size, kind)
     return out
+
+
+def as_tail(a) -> np.ndarray:
+    """Kind 0's float tail at a = |z|/9 (one call per value)."""
+    a = np.asarray(a, dtype=np.float32).ravel()
+    f = lib().gmm_oracle_as_tail
+    return np.array([f(float(v)) for v in a], dtype=np.float32)
+
+
+def as_half(d, rn) -> np.ndarray:
+    """Kind 0's signed half Phi~ - 1/2 of one component from d = b - mu and
+    rn = r/9 (one call per pair)."""
+    d = np.asarray(d, dtype=np.float32).ravel()
+    rn = np.broadcast_to(np.asarray(rn, dtype=np.float32), d.shape)
+    f = lib().gmm_oracle_as_half
+    return np.array([f(float(x), float(y)) for x, y in zip(d, rn)], dtype=np.float32)
 
 
 def ref_batch(x, which: str) -> np.ndarray:

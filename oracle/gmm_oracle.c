@@ -47,13 +47,22 @@
 
 /* ---- constants: each is the binary32 value nearest the stated real ---- */
 /* A&S 26.2.17 (Handbook of Mathematical Functions, Sec. 26.2.17). */
-static const float AS_P = 0x1.da6712p-3f;  /* 0.2316419 */
 static const float AS_B1 = 0x1.470bf4p-2f; /* 0.319381530 */
 static const float AS_B2 = -0x1.6d1f0ep-2f; /* -0.356563782 */
 static const float AS_B3 = 0x1.c80ef0p+0f; /* 1.781477937 */
 static const float AS_B4 = -0x1.d23dd4p+0f; /* -1.821255978 */
 static const float AS_B5 = 0x1.548cdep+0f; /* 1.330274429 */
-static const float INV_SQRT_2PI = 0x1.988454p-2f; /* 1/sqrt(2 pi) */
+/* A&S in the variable a = |z| / 9 (so the clamp |z| <= 9 is a <= 1), with
+ * the Gaussian density written C 2^(-x), x = (81 log2(e) / 2) a^2, C the
+ * density at 0. */
+static const float AS_P9 = 0x1.0ad9fap+1f;    /* 9 p, p = 0.2316419 */
+static const float INV_NINE = 0x1.c71c72p-4f; /* 1/9 */
+static const float AS_X = 0x1.d36ee6p+5f;     /* 81 log2(e) / 2 = 58.42915 */
+static const float TWO23_HALF = 0x1.8p+23f;   /* 1.5 * 2^23 */
+/* C (-ln 2)^k / k!, k = 0..6: Taylor coefficients of C 2^(-g) at g = 0 */
+static const float DENS_T[7] = {0x1.988454p-2f,  -0x1.1b298ep-2f, 0x1.888bdep-4f,
+                                -0x1.6aca34p-6f, 0x1.f6eefcp-9f,  -0x1.16e2b4p-11f,
+                                0x1.01beb8p-14f};
 /* logistic approximation slope (paper Sec. III-B, third candidate) */
 static const float LOGISTIC_K = 0x1.b3b646p+0f; /* 1.702 */
 /* exp~: Cody & Waite argument reduction, ln 2 split in two parts. */
@@ -108,21 +117,38 @@ float gmm_oracle_exp(float g) {
   return ldexpf(p, (int)n);
 }
 
-/* Upper tail 1 - Phi(a) for a >= 0 by A&S 26.2.17:
- * Z(a) * (b1 t + ... + b5 t^5), t = 1/(1 + p a), Z the standard normal pdf. */
-static float tail_as(float a) {
-  float u = fmaf(AS_P, a, 1.0f);
+/* Kind 0's upper tail in the scaled variable a = |z|/9, a in [0, 1]
+ * (A&S 26.2.17 with t = 1/(1 + 9p a)): the density factor C 2^(-x),
+ * x = AS_X a^2, is taken apart as x = n + g with n the integer nearest x
+ * (read off the binary32 sum 1.5 2^23 - x, whose unit is 1) and
+ * g = x - n in [-1/2, 1/2]; C 2^(-g) is the degree-6 Taylor polynomial in g,
+ * and 2^(-n) an exact power-of-two scaling. */
+float gmm_oracle_as_tail(float a) {
+  float u = fmaf(a, AS_P9, 1.0f);
   float t = 1.0f / u;
-  float q = fmaf(AS_B5, t, AS_B4);
-  q = fmaf(q, t, AS_B3);
-  q = fmaf(q, t, AS_B2);
-  q = fmaf(q, t, AS_B1);
-  q = q * t;
-  float m = a * a;
-  float g = m * -0.5f;
-  float e = gmm_oracle_exp(g);
-  float zf = INV_SQRT_2PI * e;
-  return zf * q;
+  float h = fmaf(AS_B5, t, AS_B4);
+  h = fmaf(h, t, AS_B3);
+  h = fmaf(h, t, AS_B2);
+  h = fmaf(h, t, AS_B1);
+  float q = h * t;
+  float x2 = a * a;
+  float s = fmaf(-x2, AS_X, TWO23_HALF); /* 1.5 2^23 - rint(x) */
+  float negn = s - TWO23_HALF;           /* -rint(x), exact */
+  float g = fmaf(x2, AS_X, negn);        /* x - rint(x) */
+  float e = DENS_T[6];
+  for (int k = 5; k >= 0; --k) e = fmaf(e, g, DENS_T[k]);
+  float dens = ldexpf(e, (int)negn);
+  return dens * q;
+}
+
+/* One component's contribution Phi~(z) - 1/2 to the kind-0 mixture, from
+ * d = b - mu and rn = r/9: a = min(|d| rn, 1); the tail T(a) capped so that
+ * 1/2 - T stays >= 0 (the float tail exceeds 1/2 at tiny a), signed like d:
+ * Phi(z) - 1/2 = sign(z) (1/2 - T(|z|)). */
+float gmm_oracle_as_half(float d, float rn) {
+  float a = fminf(fabsf(d) * rn, 1.0f);
+  float D = fmaxf(0.5f - gmm_oracle_as_tail(a), 0.0f);
+  return copysignf(D, d);
 }
 
 /* Upper tail of the logistic approximation: 1 - 1/(1+exp(-k a)) =
@@ -219,12 +245,15 @@ double gmm_oracle_phi_ref(double z) {
 /* Phi~(z): clamp z to [-9, 9]; Phi(-a) = tail(a) and Phi(a) = 1 - tail(a).
  * The float A&S tail slightly exceeds 1/2 for tiny a (its coefficients sum
  * to just over sqrt(pi/2) after rounding), which would make Phi~ step down
- * across z = 0; capping the tail at 1/2 keeps Phi~ non-decreasing there. */
+ * across z = 0; capping the tail at 1/2 keeps Phi~ non-decreasing there.
+ * Kind 0 enters the mixture as its signed half (above); as a function of z
+ * on its own it is 1/2 + that half with rn = 1/9. */
 float gmm_oracle_phi(float z, int32_t kind) {
   if (kind == 3) return (float)gmm_oracle_phi_ref((double)z);
+  if (kind == 0) return 0.5f + gmm_oracle_as_half(z, INV_NINE);
   z = fminf(fmaxf(z, -9.0f), 9.0f);
   float a = fabsf(z);
-  float tail = (kind == 1) ? tail_logistic(a) : (kind == 2) ? tail_polya(a) : tail_as(a);
+  float tail = (kind == 1) ? tail_logistic(a) : tail_polya(a);
   tail = fminf(tail, 0.5f);
   return (z < 0.0f) ? tail : 1.0f - tail;
 }
@@ -308,6 +337,8 @@ int gmm_oracle_params_from_raw(int32_t K, int64_t n, const float* logits,
  * zero. With param_kind 1 the planes hold raw outputs, mapped first. */
 typedef struct {
   float w[8], mu[8], r[8], s[8];
+  float rn[8]; /* r/9 (kind 0) */
+  float hw;    /* (w'_0 + ... + w'_{K-1}) / 2, summed in order (kind 0) */
 } elem_params;
 
 static void load_elem(const gmm_oracle_cfg* c, int64_t n, int64_t i, const float* w,
@@ -331,13 +362,25 @@ static void load_elem(const gmm_oracle_cfg* c, int64_t n, int64_t i, const float
     e->r[k] = 1.0f / s;
     e->w[k] = (wv[k] < 0x1p-60f) ? 0.0f : wv[k];
     e->mu[k] = mu[(int64_t)k * n + i];
+    e->rn[k] = e->r[k] * INV_NINE;
   }
+  float ws = e->w[0];
+  for (int k = 1; k < c->K; ++k) ws = ws + e->w[k];
+  e->hw = 0.5f * ws;
 }
 
 /* Mixture CDF sum_k w_k Phi~((b - mu_k)/sigma_k) at boundary j, components
- * accumulated in order with fused multiply-adds, clamped to 1. */
+ * accumulated in order with fused multiply-adds, clamped to [0, 1]. Kind 0
+ * writes each Phi~ as 1/2 + (Phi~ - 1/2): the halves sum to hw, the start
+ * of the accumulation, and each component adds w_k times its signed half. */
 static float mixture_F(const gmm_oracle_cfg* c, const elem_params* e, int64_t j) {
   float b = (float)(c->lo + j) - 0.5f;
+  if (c->cdf_kind == 0) {
+    float F = e->hw;
+    for (int k = 0; k < c->K; ++k)
+      F = fmaf(e->w[k], gmm_oracle_as_half(b - e->mu[k], e->rn[k]), F);
+    return fminf(fmaxf(F, 0.0f), 1.0f);
+  }
   float F = 0.0f;
   for (int k = 0; k < c->K; ++k) {
     float z = (b - e->mu[k]) * e->r[k];

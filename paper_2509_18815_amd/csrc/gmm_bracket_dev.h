@@ -299,7 +299,9 @@ __device__ __forceinline__ void bracket_decode_wave(
         eo.w[k] = __shfl(e.w[k], owner, 64);
         eo.mu[k] = __shfl(e.mu[k], owner, 64);
         eo.r[k] = __shfl(e.r[k], owner, 64);
+        eo.rn[k] = __shfl(e.rn[k], owner, 64);
       }
+      eo.hw = __shfl(e.hw, owner, 64);
       const uint32_t so = __shfl(slot, owner, 64);
       int32_t glo = __shfl(lo, owner, 64), ghi = __shfl(hi, owner, 64);
       uint32_t gclo = __shfl(c_lo, owner, 64), gchi = __shfl(c_hi, owner, 64);

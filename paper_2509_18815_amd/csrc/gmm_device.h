@@ -20,13 +20,28 @@
 namespace fgmm {
 
 // Abramowitz & Stegun 26.2.17 (Handbook of Mathematical Functions).
-constexpr float kAsP = 0x1.da6712p-3f;    // 0.2316419
 constexpr float kAsB1 = 0x1.470bf4p-2f;   // 0.319381530
 constexpr float kAsB2 = -0x1.6d1f0ep-2f;  // -0.356563782
 constexpr float kAsB3 = 0x1.c80ef0p+0f;   // 1.781477937
 constexpr float kAsB4 = -0x1.d23dd4p+0f;  // -1.821255978
 constexpr float kAsB5 = 0x1.548cdep+0f;   // 1.330274429
-constexpr float kInvSqrt2Pi = 0x1.988454p-2f;  // 1/sqrt(2 pi)
+// A&S component form of the mixture (kind 0): the clamp |z| <= 9 becomes
+// a = min(|b - mu| (r/9), 1), so 9 p and 81 log2(e)/2 scale a; the Gaussian
+// density C 2^(-x), x = a^2 81 log2(e)/2, splits x into n = rint(x) and
+// g = x - n in [-1/2, 1/2] (n by the round-to-integer of adding 1.5 2^23),
+// with C 2^(-g) from its Taylor polynomial of degree 6, coefficients
+// C (-ln 2)^k / k!.
+constexpr float kAsP9 = 0x1.0ad9fap+1f;   // 9 p, p = 0.2316419
+constexpr float kInv9 = 0x1.c71c72p-4f;   // 1/9
+constexpr float kAsL2 = 0x1.d36ee6p+5f;   // 81 log2(e) / 2 = 58.429150
+constexpr float kRound = 0x1.8p+23f;      // 1.5 2^23
+constexpr float kG0 = 0x1.988454p-2f;     // C
+constexpr float kG1 = -0x1.1b298ep-2f;    // -C ln 2
+constexpr float kG2 = 0x1.888bdep-4f;     // C (ln 2)^2 / 2
+constexpr float kG3 = -0x1.6aca34p-6f;    // -C (ln 2)^3 / 6
+constexpr float kG4 = 0x1.f6eefcp-9f;     // C (ln 2)^4 / 24
+constexpr float kG5 = -0x1.16e2b4p-11f;   // -C (ln 2)^5 / 120
+constexpr float kG6 = 0x1.01beb8p-14f;    // C (ln 2)^6 / 720
 constexpr float kLogisticK = 0x1.b3b646p+0f;   // 1.702, logistic slope
 // exp: Cody & Waite reduction with ln 2 split into a 16-significant-bit
 // head (so n * head is exact for |n| < 2^8) and a rounded remainder.
@@ -92,24 +107,6 @@ __device__ __forceinline__ float recip_fast(float u) {
   return fma32(e, y, y);
 }
 
-// Upper Gaussian tail 1 - Phi(a), a in [0, 9], by A&S 26.2.17:
-// Z(a) (b1 t + ... + b5 t^5), t = 1 / (1 + p a).
-template <bool kFastRecip>
-__device__ __forceinline__ float tail_as(float a) {
-  const float u = fma32(kAsP, a, 1.0f);
-  const float t = kFastRecip ? recip_fast(u) : 1.0f / u;
-  float q = fma32(kAsB5, t, kAsB4);
-  q = fma32(q, t, kAsB3);
-  q = fma32(q, t, kAsB2);
-  q = fma32(q, t, kAsB1);
-  q = q * t;
-  const float m = a * a;
-  const float g = m * -0.5f;
-  const float e = exp_tilde(g);
-  const float zf = kInvSqrt2Pi * e;
-  return zf * q;
-}
-
 // Upper tail of the logistic approximation 1/(1+exp(-1.702 a)).
 __device__ __forceinline__ float tail_logistic(float a) {
   const float g = a * -kLogisticK;
@@ -141,19 +138,55 @@ __device__ __forceinline__ float tail_polya(float a) {
   return h / (1.0f + s);
 }
 
-// Phi~(z) for the binary32 kinds (0 A&S, 1 logistic, 2 Polya): z clamped
-// to [-9, 9]; Phi(-a) = tail(a), Phi(a) = 1 - tail(a); the tail is capped at
-// 1/2 (the float A&S tail exceeds 1/2 by one ulp for tiny a), which keeps
-// Phi~ non-decreasing across z = 0.
-template <int kKind, bool kFastRecip>
+// Phi~(z) for the logistic (1) and Polya (2) kinds: z clamped to [-9, 9];
+// Phi(-a) = tail(a), Phi(a) = 1 - tail(a); the tail is capped at 1/2, which
+// keeps Phi~ non-decreasing across z = 0. (Kind 0 enters the mixture as
+// as_half below.)
+template <int kKind>
 __device__ __forceinline__ float phi_tilde(float z) {
   z = __builtin_fminf(__builtin_fmaxf(z, -9.0f), 9.0f);
   const float a = __builtin_fabsf(z);
-  float tail = (kKind == 1)   ? tail_logistic(a)
-               : (kKind == 2) ? tail_polya(a)
-                              : tail_as<kFastRecip>(a);
+  float tail = (kKind == 1) ? tail_logistic(a) : tail_polya(a);
   tail = __builtin_fminf(tail, 0.5f);
   return (z < 0.0f) ? tail : 1.0f - tail;
+}
+
+// Signed half of one A&S component, Phi~(z) - 1/2, for kind 0, from
+// d = b - mu and rn = r/9 (r = 1/sigma'):
+//   a = min(|d| rn, 1),  t = 1 / (1 + 9p a),  q = t (b1 + t (b2 + ... b5)),
+//   x2 = a a,  s = (1.5 2^23) - x2 L  (fused, = 1.5 2^23 - rint(x2 L)),
+//   n = s - 1.5 2^23 (exact),  g = x2 L + n  (fused),
+//   e = Taylor of C 2^(-g),  Q = (e 2^n) q,  D = max(1/2 - Q, 0),
+// and the result carries the sign of d. 2^n (n in [-59, 0]) is applied by
+// adding the low bits of s, which hold n, to e's exponent field: e 2^n stays
+// a normal float. D <= 1/2, so max(., 0) is the [0, 1] clamp and folds into
+// the subtraction; the clamp of a folds into its product the same way.
+template <bool kFastRecip>
+__device__ __forceinline__ float as_half(float d, float rn) {
+  const float a = __builtin_fminf(__builtin_fmaxf(__builtin_fabsf(d) * rn, 0.0f), 1.0f);
+  const float u = fma32(a, kAsP9, 1.0f);
+  const float t = kFastRecip ? recip_fast(u) : 1.0f / u;
+  float h = fma32(kAsB5, t, kAsB4);
+  h = fma32(h, t, kAsB3);
+  h = fma32(h, t, kAsB2);
+  h = fma32(h, t, kAsB1);
+  const float q = h * t;
+  const float x2 = a * a;
+  const float s = fma32(-x2, kAsL2, kRound);
+  const float n = s - kRound;
+  const float g = fma32(x2, kAsL2, n);
+  float e = fma32(kG6, g, kG5);
+  e = fma32(e, g, kG4);
+  e = fma32(e, g, kG3);
+  e = fma32(e, g, kG2);
+  e = fma32(e, g, kG1);
+  e = fma32(e, g, kG0);
+  // bits(s) = bits(1.5 2^23) + n, and bits(1.5 2^23) << 23 wraps to 0
+  const float E = __builtin_bit_cast(
+      float, __builtin_bit_cast(uint32_t, e) + (__builtin_bit_cast(uint32_t, s) << 23));
+  const float Q = E * q;
+  const float D = __builtin_fminf(__builtin_fmaxf(0.5f - Q, 0.0f), 1.0f);
+  return __builtin_copysignf(D, d);
 }
 
 // exp(g) in binary64 for g in [-686, 0]: Cody & Waite reduction, Taylor
@@ -253,9 +286,13 @@ __device__ __forceinline__ void raw_to_params(float (&w)[K], float (&s)[K]) {
 // kind keeps the clamped scale itself and divides in binary64); weights
 // below 2^-60 (including negative ones) become 0. With q.raw the planes
 // hold raw outputs, mapped first. Parameter planes are [K][n].
+// Kind 0 also keeps rn = r (1/9) per component and hw = (sum_k w'_k) / 2,
+// the sum in component order: the mixture starts from hw and adds
+// w'_k (Phi~_k - 1/2).
 template <int K>
 struct Elem {
-  float w[K], mu[K], r[K];
+  float w[K], mu[K], r[K], rn[K];
+  float hw;
 };
 
 template <int K>
@@ -287,7 +324,12 @@ __device__ __forceinline__ Elem<K> make_elem(const QCfg& q, const float (&rw)[K]
     e.r[k] = (kKind == 3) ? s : (kFastRecip ? recip_fast(s) : 1.0f / s);
     e.w[k] = (w[k] < 0x1p-60f) ? 0.0f : w[k];
     e.mu[k] = rm[k];
+    e.rn[k] = e.r[k] * kInv9;
   }
+  float ws = e.w[0];
+#pragma unroll
+  for (int k = 1; k < K; ++k) ws = ws + e.w[k];
+  e.hw = ws * 0.5f;
   return e;
 }
 
@@ -311,16 +353,21 @@ __device__ __forceinline__ uint32_t cdf_inner(const Elem<K>& e, const QCfg& q, i
   // (float)j + ((float)lo - 1/2) is the exact value lo + j - 1/2 (both
   // terms and the sum are representable), i.e. the boundary b_j.
   const float b = (float)j + q.lo_mh;
-  float F = 0.0f;
+  float F = (kKind == 0) ? e.hw : 0.0f;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const float z = (b - e.mu[k]) * e.r[k];
-    F = fma32(e.w[k], phi_tilde<kKind, kFastRecip>(z), F);
+    if constexpr (kKind == 0) {
+      F = fma32(e.w[k], as_half<kFastRecip>(b - e.mu[k], e.rn[k]), F);
+    } else {
+      const float z = (b - e.mu[k]) * e.r[k];
+      F = fma32(e.w[k], phi_tilde<kKind>(z), F);
+    }
   }
-  // min(F, 1): F >= 0, so clamping to [0, 1] is the same value, and the
-  // clamp folds into the last fused multiply-add as its output modifier
+  // F clamped to [0, 1] (min(F, 1) of the contract; kind 0's sum of
+  // signed halves can round a few ulps below 0), folded into the last
+  // fused multiply-add as its output modifier
   F = __builtin_fminf(__builtin_fmaxf(F, 0.0f), 1.0f);
-  // F >= 0 (w' >= 0 and Phi~ >= 0), so the truncating conversion is the floor
+  // F >= 0 after the clamp, so the truncating conversion is the floor
   return (uint32_t)j + (uint32_t)(F * q.span);
 }
 

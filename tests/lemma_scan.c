@@ -1,13 +1,14 @@
 /*
- * Exhaustive check behind the monotonicity lemma of the quantized CDF.
+ * Exhaustive checks behind the monotonicity lemma of the quantized CDF.
  *
- * For every binary32 a in [0, 9] it compares the oracle's float upper tail
- * (Phi~(-a), the branch used for z < 0) with the same approximant evaluated
- * in binary64, and records the largest relative difference and the largest
- * float tail. With the hazard bound -d ln Q/da >= h of the approximant
- * (checked separately in binary64) this proves that the float tail strictly
- * decreases across every step of at least 2^-11 in a, and the bound
- * tail <= 1/2 makes the step across z = 0 monotone.
+ * Kind 0 (A&S): for every binary32 a in (0, 1] (a = |z|/9) it compares the
+ * oracle's float tail with the same approximant in binary64 and records the
+ * largest relative difference and the extreme tails. Logistic kind: the
+ * same for the float tail Phi~(-a) over every binary32 a in [0, 9]. With the
+ * hazard bound -d ln T/da >= h of the approximant (checked separately in
+ * binary64) this proves that the float tail strictly decreases across every
+ * step of at least d in a (2^-14 for kind 0, 2^-11 for the logistic kind);
+ * the cap at 1/2 makes the step across z = 0 monotone.
  *
  * Built and run by the CPU tests against liboracle.so.
  */
@@ -18,22 +19,13 @@
 
 float gmm_oracle_phi(float z, int32_t kind);
 
-static double tail64(double a, int kind) {
-  if (kind == 1) {
-    double e = exp(-(double)0x1.b3b646p+0f * a);
-    return e / (1.0 + e);
-  }
-  double t = 1.0 / (1.0 + (double)0x1.da6712p-3f * a);
-  double q = (double)0x1.548cdep+0f;
-  q = q * t + (double)-0x1.d23dd4p+0f;
-  q = q * t + (double)0x1.c80ef0p+0f;
-  q = q * t + (double)-0x1.6d1f0ep-2f;
-  q = q * t + (double)0x1.470bf4p-2f;
-  q = q * t;
-  return exp(-0.5 * a * a) / sqrt(2.0 * 3.14159265358979323846) * q;
+/* The logistic tail (kind 1) in binary64 with the binary32 slope. */
+static double tail64(double a) {
+  double e = exp(-(double)0x1.b3b646p+0f * a);
+  return e / (1.0 + e);
 }
 
-/* Scans the float bit patterns [lo_bits, hi_bits] (non-negative floats).
+/* Logistic kind: scans the float bit patterns [lo_bits, hi_bits] (non-negative floats).
  * out[0] = max relative error, out[1] = max float tail (a > 0),
  * out[2] = a at the max relative error, out[3] = min float tail (the tail at
  * the clamp a = 9 must be the smallest, since a neighbouring boundary can
@@ -50,7 +42,7 @@ void lemma_scan(uint32_t lo_bits, uint32_t hi_bits, int kind, double* out) {
       memcpy(&a, &bits, 4);
       if (a == 0.0f) continue;
       float tf = gmm_oracle_phi(-a, kind);
-      double td = tail64((double)a, kind);
+      double td = tail64((double)a);
       double rel = fabs((double)tf - td) / td;
       if (rel > lrel) { lrel = rel; larg = a; }
       if (tf > ltail) ltail = tf;
@@ -70,6 +62,54 @@ void lemma_scan(uint32_t lo_bits, uint32_t hi_bits, int kind, double* out) {
 }
 
 float gmm_oracle_exp(float g);
+float gmm_oracle_as_tail(float a);
+
+/* Kind 0's tail approximant in binary64, in the scaled variable a = |z|/9
+ * with the binary32 constants of the contract: C 2^(-x a^2) q(t),
+ * t = 1/(1 + 9p a), q the A&S polynomial, C = 1/sqrt(2 pi). */
+static double as_tail64(double a) {
+  double t = 1.0 / (1.0 + (double)0x1.0ad9fap+1f * a);
+  double q = (double)0x1.548cdep+0f;
+  q = q * t + (double)-0x1.d23dd4p+0f;
+  q = q * t + (double)0x1.c80ef0p+0f;
+  q = q * t + (double)-0x1.6d1f0ep-2f;
+  q = q * t + (double)0x1.470bf4p-2f;
+  q = q * t;
+  return exp2(-(double)0x1.d36ee6p+5f * a * a) / sqrt(2.0 * 3.14159265358979323846) * q;
+}
+
+/* Every float a in (0, a(hi_bits)] of kind 0's float tail T(a) (before the
+ * cap): out[0] = largest relative error against as_tail64, out[1] = largest
+ * T, out[2] = a there, out[3] = smallest T. */
+void as_lemma_scan(uint32_t hi_bits, double* out) {
+  double max_rel = 0.0, max_tail = 0.0, arg = 0.0, min_tail = 1.0;
+#pragma omp parallel
+  {
+    double lrel = 0.0, ltail = 0.0, larg = 0.0, lmin = 1.0;
+#pragma omp for schedule(static, 1 << 16)
+    for (int64_t b = 1; b <= (int64_t)hi_bits; ++b) {
+      uint32_t bits = (uint32_t)b;
+      float a;
+      memcpy(&a, &bits, 4);
+      float tf = gmm_oracle_as_tail(a);
+      double td = as_tail64((double)a);
+      double rel = fabs((double)tf - td) / td;
+      if (rel > lrel) lrel = rel;
+      if (tf > ltail) { ltail = tf; larg = a; }
+      if (tf < lmin) lmin = tf;
+    }
+#pragma omp critical
+    {
+      if (lrel > max_rel) max_rel = lrel;
+      if (ltail > max_tail) { max_tail = ltail; arg = larg; }
+      if (lmin < min_tail) min_tail = lmin;
+    }
+  }
+  out[0] = max_rel;
+  out[1] = max_tail;
+  out[2] = arg;
+  out[3] = min_tail;
+}
 
 static float f_of(uint32_t bits) {
   float a;

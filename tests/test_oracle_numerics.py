@@ -113,41 +113,68 @@ def _lemma_lib():
     return ctypes.CDLL(so)
 
 
+AS_B = [float(np.float32(v)) for v in (0.319381530, -0.356563782, 1.781477937,
+                                        -1.821255978, 1.330274429)]
+
+
 def _hazard_min(kind, n=2_000_001):
-    """min over [0, 9] of -d ln tail(a)/da for the binary64 approximant with
-    the binary32 constants (analytic derivative)."""
-    a = np.linspace(0.0, 9.0, n)
+    """min of -d ln tail(a)/da for the binary64 approximant with the binary32
+    constants (analytic derivative): kind 0 over a = |z|/9 in [0, 1], the
+    logistic kind over a = |z| in [0, 9]. Also returns the grid step."""
     if kind == 1:
+        a = np.linspace(0.0, 9.0, n)
         k = float(np.float32(1.702))
         return float((k / (1.0 + np.exp(-k * a))).min()), a[1] - a[0]
-    p = float(np.float32(0.2316419))
-    b = [float(np.float32(v)) for v in (0.319381530, -0.356563782, 1.781477937,
-                                        -1.821255978, 1.330274429)]
-    t = 1.0 / (1.0 + p * a)
-    q = sum(bi * t ** (i + 1) for i, bi in enumerate(b))
-    dq = sum((i + 1) * bi * t ** i for i, bi in enumerate(b))
-    h = a + p * t * t * dq / q
+    a = np.linspace(0.0, 1.0, n)
+    p9 = float(np.float32(9 * 0.2316419))
+    x = float(np.float32(81.0 / (2.0 * np.log(2.0))))   # 81 log2(e) / 2
+    t = 1.0 / (1.0 + p9 * a)
+    q = sum(bi * t ** (i + 1) for i, bi in enumerate(AS_B))
+    dq = sum((i + 1) * bi * t ** i for i, bi in enumerate(AS_B))
+    h = 2.0 * x * np.log(2.0) * a + p9 * t * t * dq / q
     return float(h.min()), a[1] - a[0]
 
 
-@pytest.mark.parametrize("kind", [0, 1])
-def test_monotonicity_lemma_exhaustive(orc, kind):
-    """Every float a in [0, 9]: the float tail's relative error E against the
-    binary64 approximant, with hazard h, gives exp(-h d)(1+E)/(1-E) < 1 for
-    the smallest boundary step d = 2^-11 in z, so the float tail strictly
-    decreases across steps; tail <= 1/2 orders the two branches at z = 0;
-    the tail at the clamp a = 9 is the global minimum."""
+def test_monotonicity_lemma_exhaustive_as(orc):
+    """Kind 0, every float a in (0, 1] (a = min(|b - mu| r/9, 1)): the float
+    tail's relative error E against the binary64 approximant, with hazard
+    h, gives exp(-h d)(1+E)/(1-E) < 1 for the smallest step d between the a
+    of two consecutive boundaries: |b - mu| moves by at least 1 - 2^-10 and
+    r/9 >= 2^-10/9, so d >= (1 - 2^-10) 2^-10/9 - 2^-24 > 2^-14. The float
+    tail thus strictly decreases across steps; the tail at the clamp a = 1
+    is the global minimum; 1/2 - T is floored at 0, which orders the two
+    signs at z = 0."""
+    L = _lemma_lib()
+    out = (ctypes.c_double * 4)()
+    hi = struct.unpack("<I", struct.pack("<f", 1.0))[0]
+    L.as_lemma_scan(ctypes.c_uint32(hi), out)
+    E, max_tail, min_tail = out[0], out[1], out[3]
+    h, gap = _hazard_min(0)
+    h -= 200.0 * gap        # the hazard's slope in a is below 200 on [0, 1]
+    d = 2.0 ** -14
+    assert (1 - 2.0 ** -10) * 2.0 ** -10 / 9 - 2.0 ** -24 > d
+    assert E < 2.5e-6, E      # the rounding of a^2, amplified by the exponent x <= 58.4
+    assert np.exp(-h * d) * (1 + E) / (1 - E) < 1.0, (h, E)
+    assert min_tail == float(orc.as_tail(np.float32([1.0]))[0])
+    # the cap is active only where the float tail passes 1/2, next to a = 0
+    assert 0.5 < max_tail <= 0.5 + 2.0 ** -24 and out[2] < 1e-6
+
+
+def test_monotonicity_lemma_exhaustive_logistic(orc):
+    """Logistic kind, every float a in [0, 9]: as above with the step 2^-11
+    in z; tail <= 1/2 orders the two branches at z = 0; the tail at the
+    clamp a = 9 is the global minimum."""
     L = _lemma_lib()
     out = (ctypes.c_double * 4)()
     hi = struct.unpack("<I", struct.pack("<f", 9.0))[0]
-    L.lemma_scan(ctypes.c_uint32(0), ctypes.c_uint32(hi), ctypes.c_int(kind), out)
+    L.lemma_scan(ctypes.c_uint32(0), ctypes.c_uint32(hi), ctypes.c_int(1), out)
     E, max_tail, _, min_tail = out[0], out[1], out[2], out[3]
-    h, gap = _hazard_min(kind)
+    h, gap = _hazard_min(1)
     h -= 2.0 * gap          # the hazard's slope is below 2 on [0, 9]
     d = 2.0 ** -11
     assert np.exp(-h * d) * (1 + E) / (1 - E) < 1.0, (h, E)
     assert max_tail <= 0.5
-    assert min_tail == float(orc.phi(np.float32([-9.0]), kind)[0])
+    assert min_tail == float(orc.phi(np.float32([-9.0]), 1)[0])
 
 
 @pytest.mark.parametrize("kind", [0, 1])
