@@ -35,12 +35,12 @@ VALU_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9
 
 def flops_per_eval(K: int) -> int:
     """Algorithmic binary32 flops of one A&S mixture CDF evaluation (fma =
-    2): per component 40 (b - mu: 1, a = min(|d| r/9, 1): 2, u: 2, 1/u: 1,
-    polynomial: 9, a^2: 1, split of the exponent: 5, degree-6 polynomial of
-    the density: 12, 2^n scaling: 1, density times polynomial: 1, 1/2 - T
+    2): per component 38 (b - mu: 1, a = min(|d| r/9, 1): 2, u: 2, 1/u: 1,
+    polynomial: 9, a^2: 1, split of the exponent: 5, degree-5 polynomial of
+    the density: 10, 2^n scaling: 1, density times polynomial: 1, 1/2 - T
     floored at 0: 2, sign: 1, mixture fma: 2) plus 4 per evaluation
     (boundary, clamp, scale, floor)."""
-    return 40 * K + 4
+    return 38 * K + 4
 
 
 def decode_flops_per_symbol(K: int, N: int) -> int:

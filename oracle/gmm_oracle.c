@@ -59,10 +59,14 @@ static const float AS_P9 = 0x1.0ad9fap+1f;    /* 9 p, p = 0.2316419 */
 static const float INV_NINE = 0x1.c71c72p-4f; /* 1/9 */
 static const float AS_X = 0x1.d36ee6p+5f;     /* 81 log2(e) / 2 = 58.42915 */
 static const float TWO23_HALF = 0x1.8p+23f;   /* 1.5 * 2^23 */
-/* C (-ln 2)^k / k!, k = 0..6: Taylor coefficients of C 2^(-g) at g = 0 */
-static const float DENS_T[7] = {0x1.988454p-2f,  -0x1.1b298ep-2f, 0x1.888bdep-4f,
-                                -0x1.6aca34p-6f, 0x1.f6eefcp-9f,  -0x1.16e2b4p-11f,
-                                0x1.01beb8p-14f};
+/* C 2^(-g) on [-1/2, 1/2]: the degree-7 Taylor polynomial sum_k c_k g^k,
+ * c_k = C (-ln 2)^k / k!, economized (Lanczos) to degree 5 by replacing
+ * g^7 and g^6 with their Chebyshev expansions on [-1/2, 1/2] less the T7
+ * and T6 terms (g^7 = T7(2g)/8192 + (7/16) g^5 - (7/128) g^3 + (7/4096) g;
+ * g^6 = T6(2g)/2048 + (3/8) g^4 - (9/256) g^2 + 1/2048):
+ * coefficient k below is the binary32 nearest the resulting real. */
+static const float DENS_T[6] = {0x1.988456p-2f,  -0x1.1b2990p-2f, 0x1.88899ap-4f,
+                                -0x1.6ac8cep-6f, 0x1.f9f438p-9f,  -0x1.184804p-11f};
 /* logistic approximation slope (paper Sec. III-B, third candidate) */
 static const float LOGISTIC_K = 0x1.b3b646p+0f; /* 1.702 */
 /* exp~: Cody & Waite argument reduction, ln 2 split in two parts. */
@@ -121,8 +125,8 @@ float gmm_oracle_exp(float g) {
  * (A&S 26.2.17 with t = 1/(1 + 9p a)): the density factor C 2^(-x),
  * x = AS_X a^2, is taken apart as x = n + g with n the integer nearest x
  * (read off the binary32 sum 1.5 2^23 - x, whose unit is 1) and
- * g = x - n in [-1/2, 1/2]; C 2^(-g) is the degree-6 Taylor polynomial in g,
- * and 2^(-n) an exact power-of-two scaling. */
+ * g = x - n in [-1/2, 1/2]; C 2^(-g) is the degree-5 polynomial above, and
+ * 2^(-n) an exact power-of-two scaling. */
 float gmm_oracle_as_tail(float a) {
   float u = fmaf(a, AS_P9, 1.0f);
   float t = 1.0f / u;
@@ -135,8 +139,8 @@ float gmm_oracle_as_tail(float a) {
   float s = fmaf(-x2, AS_X, TWO23_HALF); /* 1.5 2^23 - rint(x) */
   float negn = s - TWO23_HALF;           /* -rint(x), exact */
   float g = fmaf(x2, AS_X, negn);        /* x - rint(x) */
-  float e = DENS_T[6];
-  for (int k = 5; k >= 0; --k) e = fmaf(e, g, DENS_T[k]);
+  float e = DENS_T[5];
+  for (int k = 4; k >= 0; --k) e = fmaf(e, g, DENS_T[k]);
   float dens = ldexpf(e, (int)negn);
   return dens * q;
 }

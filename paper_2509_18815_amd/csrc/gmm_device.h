@@ -28,20 +28,22 @@ constexpr float kAsB5 = 0x1.548cdep+0f;   // 1.330274429
 // A&S component form of the mixture (kind 0): the clamp |z| <= 9 becomes
 // a = min(|b - mu| (r/9), 1), so 9 p and 81 log2(e)/2 scale a; the Gaussian
 // density C 2^(-x), x = a^2 81 log2(e)/2, splits x into n = rint(x) and
-// g = x - n in [-1/2, 1/2] (n by the round-to-integer of adding 1.5 2^23),
-// with C 2^(-g) from its Taylor polynomial of degree 6, coefficients
-// C (-ln 2)^k / k!.
+// g = x - n in [-1/2, 1/2] (n by the round-to-integer of adding 1.5 2^23).
+// C 2^(-g) is the degree-7 Taylor polynomial of C e^(-g ln 2) economized
+// to degree 5 on [-1/2, 1/2] with the Chebyshev polynomials T7 and T6
+// (Lanczos): with L = ln 2, c_k = C (-L)^k / k!,
+//   G0 = c0 + c6/2048, G1 = c1 + (14/8192) c7, G2 = c2 - (72/2048) c6,
+//   G3 = c3 - (448/8192) c7, G4 = c4 + (768/2048) c6, G5 = c5 + (3584/8192) c7.
 constexpr float kAsP9 = 0x1.0ad9fap+1f;   // 9 p, p = 0.2316419
 constexpr float kInv9 = 0x1.c71c72p-4f;   // 1/9
 constexpr float kAsL2 = 0x1.d36ee6p+5f;   // 81 log2(e) / 2 = 58.429150
 constexpr float kRound = 0x1.8p+23f;      // 1.5 2^23
-constexpr float kG0 = 0x1.988454p-2f;     // C
-constexpr float kG1 = -0x1.1b298ep-2f;    // -C ln 2
-constexpr float kG2 = 0x1.888bdep-4f;     // C (ln 2)^2 / 2
-constexpr float kG3 = -0x1.6aca34p-6f;    // -C (ln 2)^3 / 6
-constexpr float kG4 = 0x1.f6eefcp-9f;     // C (ln 2)^4 / 24
-constexpr float kG5 = -0x1.16e2b4p-11f;   // -C (ln 2)^5 / 120
-constexpr float kG6 = 0x1.01beb8p-14f;    // C (ln 2)^6 / 720
+constexpr float kG0 = 0x1.988456p-2f;
+constexpr float kG1 = -0x1.1b2990p-2f;
+constexpr float kG2 = 0x1.88899ap-4f;
+constexpr float kG3 = -0x1.6ac8cep-6f;
+constexpr float kG4 = 0x1.f9f438p-9f;
+constexpr float kG5 = -0x1.184804p-11f;
 constexpr float kLogisticK = 0x1.b3b646p+0f;   // 1.702, logistic slope
 // exp: Cody & Waite reduction with ln 2 split into a 16-significant-bit
 // head (so n * head is exact for |n| < 2^8) and a rounded remainder.
@@ -156,7 +158,7 @@ __device__ __forceinline__ float phi_tilde(float z) {
 //   a = min(|d| rn, 1),  t = 1 / (1 + 9p a),  q = t (b1 + t (b2 + ... b5)),
 //   x2 = a a,  s = (1.5 2^23) - x2 L  (fused, = 1.5 2^23 - rint(x2 L)),
 //   n = s - 1.5 2^23 (exact),  g = x2 L + n  (fused),
-//   e = Taylor of C 2^(-g),  Q = (e 2^n) q,  D = max(1/2 - Q, 0),
+//   e = polynomial of C 2^(-g),  Q = (e 2^n) q,  D = max(1/2 - Q, 0),
 // and the result carries the sign of d. 2^n (n in [-59, 0]) is applied by
 // adding the low bits of s, which hold n, to e's exponent field: e 2^n stays
 // a normal float. D <= 1/2, so max(., 0) is the [0, 1] clamp and folds into
@@ -175,8 +177,7 @@ __device__ __forceinline__ float as_half(float d, float rn) {
   const float s = fma32(-x2, kAsL2, kRound);
   const float n = s - kRound;
   const float g = fma32(x2, kAsL2, n);
-  float e = fma32(kG6, g, kG5);
-  e = fma32(e, g, kG4);
+  float e = fma32(kG5, g, kG4);
   e = fma32(e, g, kG3);
   e = fma32(e, g, kG2);
   e = fma32(e, g, kG1);
