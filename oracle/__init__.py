@@ -57,7 +57,7 @@ def lib():
         sigs = {
             "gmm_oracle_phi": (ctypes.c_float, [ctypes.c_float, i32]),
             "gmm_oracle_exp": (ctypes.c_float, [ctypes.c_float]),
-            "gmm_oracle_as_tail": (ctypes.c_float, [ctypes.c_float]),
+            "gmm_oracle_as_tail": (ctypes.c_double, [ctypes.c_float]),
             "gmm_oracle_as_half": (ctypes.c_float, [ctypes.c_float, ctypes.c_float]),
             "gmm_oracle_phi_batch": (None, [P, P, i64, i32]),
             "gmm_oracle_exp_batch": (None, [P, P, i64]),
@@ -109,10 +109,11 @@ def phi(z, kind=0) -> np.ndarray:
 
 
 def as_tail(a) -> np.ndarray:
-    """Kind 0's float tail at a = |z|/9 (one call per value)."""
+    """Kind 0's tail at a = |z|/9, the exact (binary64) product of its two
+    binary32 factors (one call per value)."""
     a = np.asarray(a, dtype=np.float32).ravel()
     f = lib().gmm_oracle_as_tail
-    return np.array([f(float(v)) for v in a], dtype=np.float32)
+    return np.array([f(float(v)) for v in a], dtype=np.float64)
 
 
 def as_half(d, rn) -> np.ndarray:

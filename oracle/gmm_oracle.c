@@ -122,36 +122,48 @@ float gmm_oracle_exp(float g) {
 }
 
 /* Kind 0's upper tail in the scaled variable a = |z|/9, a in [0, 1]
- * (A&S 26.2.17 with t = 1/(1 + 9p a)): the density factor C 2^(-x),
- * x = AS_X a^2, is taken apart as x = n + g with n the integer nearest x
- * (read off the binary32 sum 1.5 2^23 - x, whose unit is 1) and
+ * (A&S 26.2.17 with t = 1/(1 + 9p a)), as the two binary32 factors whose
+ * product it is: the polynomial factor q and the density factor C 2^(-x),
+ * x = AS_X a^2. The density is taken apart as x = n + g with n the integer
+ * nearest x (read off the binary32 sum 1.5 2^23 - x, whose unit is 1) and
  * g = x - n in [-1/2, 1/2]; C 2^(-g) is the degree-5 polynomial above, and
  * 2^(-n) an exact power-of-two scaling. */
-float gmm_oracle_as_tail(float a) {
+static void as_factors(float a, float* dens, float* q) {
   float u = fmaf(a, AS_P9, 1.0f);
   float t = 1.0f / u;
   float h = fmaf(AS_B5, t, AS_B4);
   h = fmaf(h, t, AS_B3);
   h = fmaf(h, t, AS_B2);
   h = fmaf(h, t, AS_B1);
-  float q = h * t;
+  *q = h * t;
   float x2 = a * a;
   float s = fmaf(-x2, AS_X, TWO23_HALF); /* 1.5 2^23 - rint(x) */
   float negn = s - TWO23_HALF;           /* -rint(x), exact */
   float g = fmaf(x2, AS_X, negn);        /* x - rint(x) */
   float e = DENS_T[5];
   for (int k = 4; k >= 0; --k) e = fmaf(e, g, DENS_T[k]);
-  float dens = ldexpf(e, (int)negn);
-  return dens * q;
+  *dens = ldexpf(e, (int)negn);
+}
+
+/* The tail as the exact product of its two factors (a binary64 holds the
+ * product of two binary32 values exactly); the mixture uses it only inside
+ * the fused 1/2 - dens q. */
+double gmm_oracle_as_tail(float a) {
+  float dens, q;
+  as_factors(a, &dens, &q);
+  return (double)dens * (double)q;
 }
 
 /* One component's contribution Phi~(z) - 1/2 to the kind-0 mixture, from
- * d = b - mu and rn = r/9: a = min(|d| rn, 1); the tail T(a) capped so that
- * 1/2 - T stays >= 0 (the float tail exceeds 1/2 at tiny a), signed like d:
- * Phi(z) - 1/2 = sign(z) (1/2 - T(|z|)). */
+ * d = b - mu and rn = r/9: a = min(|d| rn, 1); D = 1/2 - T rounded once
+ * (a fused multiply-add of the two factors) and floored at 0 (the tail
+ * exceeds 1/2 at tiny a), signed like d: Phi(z) - 1/2 = sign(z) (1/2 -
+ * T(|z|)). */
 float gmm_oracle_as_half(float d, float rn) {
   float a = fminf(fabsf(d) * rn, 1.0f);
-  float D = fmaxf(0.5f - gmm_oracle_as_tail(a), 0.0f);
+  float dens, q;
+  as_factors(a, &dens, &q);
+  float D = fmaxf(fmaf(-dens, q, 0.5f), 0.0f);
   return copysignf(D, d);
 }
 

@@ -36,9 +36,10 @@ typedef struct {
 
 /* Gaussian CDF approximation Phi~(z), binary32 contract arithmetic. */
 float gmm_oracle_phi(float z, int32_t kind);
-/* Kind 0 (A&S 26.2.17): the float upper tail in a = |z|/9, a in [0, 1], and
- * one component's signed half Phi~ - 1/2 from d = b - mu and rn = r/9. */
-float gmm_oracle_as_tail(float a);
+/* Kind 0 (A&S 26.2.17): the upper tail in a = |z|/9, a in [0, 1] (the exact
+ * product of its two binary32 factors), and one component's signed half
+ * Phi~ - 1/2 from d = b - mu and rn = r/9. */
+double gmm_oracle_as_tail(float a);
 float gmm_oracle_as_half(float d, float rn);
 /* exp~(g) for g in [-51.6, 7]: Cody-Waite reduction + degree-7 Taylor. */
 float gmm_oracle_exp(float g);

@@ -158,11 +158,12 @@ __device__ __forceinline__ float phi_tilde(float z) {
 //   a = min(|d| rn, 1),  t = 1 / (1 + 9p a),  q = t (b1 + t (b2 + ... b5)),
 //   x2 = a a,  s = (1.5 2^23) - x2 L  (fused, = 1.5 2^23 - rint(x2 L)),
 //   n = s - 1.5 2^23 (exact),  g = x2 L + n  (fused),
-//   e = polynomial of C 2^(-g),  Q = (e 2^n) q,  D = max(1/2 - Q, 0),
+//   e = polynomial of C 2^(-g),  D = max(fma(-(e 2^n), q, 1/2), 0),
 // and the result carries the sign of d. 2^n (n in [-59, 0]) is applied by
 // adding the low bits of s, which hold n, to e's exponent field: e 2^n stays
 // a normal float. D <= 1/2, so max(., 0) is the [0, 1] clamp and folds into
-// the subtraction; the clamp of a folds into its product the same way.
+// the fused multiply-add; the clamp of a folds into its product the same
+// way.
 template <bool kFastRecip>
 __device__ __forceinline__ float as_half(float d, float rn) {
   const float a = __builtin_fminf(__builtin_fmaxf(__builtin_fabsf(d) * rn, 0.0f), 1.0f);
@@ -185,8 +186,7 @@ __device__ __forceinline__ float as_half(float d, float rn) {
   // bits(s) = bits(1.5 2^23) + n, and bits(1.5 2^23) << 23 wraps to 0
   const float E = __builtin_bit_cast(
       float, __builtin_bit_cast(uint32_t, e) + (__builtin_bit_cast(uint32_t, s) << 23));
-  const float Q = E * q;
-  const float D = __builtin_fminf(__builtin_fmaxf(0.5f - Q, 0.0f), 1.0f);
+  const float D = __builtin_fminf(__builtin_fmaxf(fma32(-E, q, 0.5f), 0.0f), 1.0f);
   return __builtin_copysignf(D, d);
 }
 

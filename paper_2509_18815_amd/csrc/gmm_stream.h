@@ -47,11 +47,45 @@ __device__ __forceinline__ int free_rounds(int rounds, int32_t N) {
   return nfree;
 }
 
-// nfree = free_rounds(rounds, N), computed once by the caller.
-template <int K, int kKind, bool kFast>
+// The same search with the round counts fixed at compile time: the rounds
+// are straight-line code (no loop counters or back-edges between them).
+template <int K, int kKind, bool kFast, int kRounds, int kFree>
+__device__ __forceinline__ int32_t search_fixed(const Elem<K>& e, const QCfg& q, uint32_t slot,
+                                                uint32_t& c_lo, uint32_t& c_hi) {
+  int32_t lo = 0;
+  c_lo = 0;
+  c_hi = q.M;
+#pragma unroll
+  for (int i = 0; i < kRounds; ++i) {
+    const int32_t mid = lo + (1 << (kRounds - 1 - i));
+    const uint32_t c = (i < kFree) ? cdf_inner<K, kKind, kFast>(e, q, mid)
+                                   : cdf_upper<K, kKind, kFast>(e, q, mid);
+    const bool right = slot >= c;
+    lo = right ? mid : lo;
+    c_lo = right ? c : c_lo;
+    c_hi = right ? c_hi : c;
+  }
+  return lo;
+}
+
+// nfree = free_rounds(rounds, N), computed once by the caller. With
+// kStraight (A&S kind) the alphabets of 256, 511 and 1023 symbols take the
+// straight-line form (a wavefront-uniform branch on the kernel's
+// arguments). It pays where one wavefront per SIMD leaves the loop's scalar
+// and branch instructions exposed; it also holds more registers, so the
+// batched kernels, which rely on several wavefronts per SIMD, keep the loop.
+template <int K, int kKind, bool kFast, bool kStraight = false>
 __device__ __forceinline__ int32_t search_bs(const Elem<K>& e, const QCfg& q, int rounds,
                                              int nfree, uint32_t slot, uint32_t& c_lo,
                                              uint32_t& c_hi) {
+  if constexpr (kKind == 0 && kStraight) {
+    if (rounds == 9 && nfree == 8)
+      return search_fixed<K, kKind, kFast, 9, 8>(e, q, slot, c_lo, c_hi);
+    if (rounds == 8 && nfree == 8)
+      return search_fixed<K, kKind, kFast, 8, 8>(e, q, slot, c_lo, c_hi);
+    if (rounds == 10 && nfree == 9)
+      return search_fixed<K, kKind, kFast, 10, 9>(e, q, slot, c_lo, c_hi);
+  }
   int32_t lo = 0;
   c_lo = 0;
   c_hi = q.M;
@@ -358,7 +392,8 @@ __device__ __forceinline__ float opaque_copy(float v) {
 // With kGather the coded sequence is the subset idx[0..n) of a latent of
 // n_total elements: pass position i reads its parameters at element idx[i]
 // of the [K][n_total] planes and writes its symbol to sym[idx[i]].
-template <int K, int kKind, bool kFast, int L, bool kGather = false>
+// kStraight selects the straight-line binary search (search_bs).
+template <int K, int kKind, bool kFast, int L, bool kGather = false, bool kStraight = false>
 __device__ __forceinline__ bool decode_stream(const QCfg& q, int P, int rounds, int64_t n,
                                               int64_t S, int64_t s, int g,
                                               const uint16_t* __restrict__ bs, int64_t total_words,
@@ -426,7 +461,7 @@ __device__ __forceinline__ bool decode_stream(const QCfg& q, int P, int rounds, 
         const Elem<K> e = make_elem<K, kFast, kKind>(q, cw, cm, cs);
         int32_t j;
         if (L == 1)
-          j = search_bs<K, kKind, kFast>(e, q, rounds, nfree, slot, cl, ch);
+          j = search_bs<K, kKind, kFast, kStraight>(e, q, rounds, nfree, slot, cl, ch);
         else
           j = search_group<K, kKind, kFast, L>(e, q, rounds, slot, g, gbase, gmask, 0, q.N, cl,
                                                ch);

@@ -62,7 +62,7 @@ void lemma_scan(uint32_t lo_bits, uint32_t hi_bits, int kind, double* out) {
 }
 
 float gmm_oracle_exp(float g);
-float gmm_oracle_as_tail(float a);
+double gmm_oracle_as_tail(float a);
 
 /* Kind 0's tail approximant in binary64, in the scaled variable a = |z|/9
  * with the binary32 constants of the contract: C 2^(-x a^2) q(t),
@@ -78,9 +78,10 @@ static double as_tail64(double a) {
   return exp2(-(double)0x1.d36ee6p+5f * a * a) / sqrt(2.0 * 3.14159265358979323846) * q;
 }
 
-/* Every float a in (0, a(hi_bits)] of kind 0's float tail T(a) (before the
- * cap): out[0] = largest relative error against as_tail64, out[1] = largest
- * T, out[2] = a there, out[3] = smallest T. */
+/* Every float a in (0, a(hi_bits)] of kind 0's tail T(a) (the exact product
+ * of its two float factors, before the cap): out[0] = largest relative error
+ * against as_tail64, out[1] = largest T, out[2] = a there, out[3] = smallest
+ * T. */
 void as_lemma_scan(uint32_t hi_bits, double* out) {
   double max_rel = 0.0, max_tail = 0.0, arg = 0.0, min_tail = 1.0;
 #pragma omp parallel
@@ -91,9 +92,9 @@ void as_lemma_scan(uint32_t hi_bits, double* out) {
       uint32_t bits = (uint32_t)b;
       float a;
       memcpy(&a, &bits, 4);
-      float tf = gmm_oracle_as_tail(a);
+      double tf = gmm_oracle_as_tail(a);
       double td = as_tail64((double)a);
-      double rel = fabs((double)tf - td) / td;
+      double rel = fabs(tf - td) / td;
       if (rel > lrel) lrel = rel;
       if (tf > ltail) { ltail = tf; larg = a; }
       if (tf < lmin) lmin = tf;

@@ -141,9 +141,10 @@ def test_monotonicity_lemma_exhaustive_as(orc):
     h, gives exp(-h d)(1+E)/(1-E) < 1 for the smallest step d between the a
     of two consecutive boundaries: |b - mu| moves by at least 1 - 2^-10 and
     r/9 >= 2^-10/9, so d >= (1 - 2^-10) 2^-10/9 - 2^-24 > 2^-14. The float
-    tail thus strictly decreases across steps; the tail at the clamp a = 1
-    is the global minimum; 1/2 - T is floored at 0, which orders the two
-    signs at z = 0."""
+    tail (the exact product of its two float factors) thus strictly
+    decreases across steps, and D = RN(1/2 - T), one fused multiply-add,
+    does not decrease; the tail at the clamp a = 1 is the global minimum;
+    D is floored at 0, which orders the two signs at z = 0."""
     L = _lemma_lib()
     out = (ctypes.c_double * 4)()
     hi = struct.unpack("<I", struct.pack("<f", 1.0))[0]
@@ -155,7 +156,7 @@ def test_monotonicity_lemma_exhaustive_as(orc):
     assert (1 - 2.0 ** -10) * 2.0 ** -10 / 9 - 2.0 ** -24 > d
     assert E < 2.5e-6, E      # the rounding of a^2, amplified by the exponent x <= 58.4
     assert np.exp(-h * d) * (1 + E) / (1 - E) < 1.0, (h, E)
-    assert min_tail == float(orc.as_tail(np.float32([1.0]))[0])
+    assert min_tail == orc.as_tail(np.float32([1.0]))[0]
     # the cap is active only where the float tail passes 1/2, next to a = 0
     assert 0.5 < max_tail <= 0.5 + 2.0 ** -22 and out[2] < 1e-6
 
