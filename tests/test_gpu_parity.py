@@ -192,6 +192,40 @@ def test_4k_latent_sampled_streams(api, orc):
         assert st == orc.OK and np.array_equal(odec, sub[0])
 
 
+@pytest.mark.parametrize("n,S,K,lo,hi,kind", [
+    (2 * 65536 + 101, 65536, 3, -255, 255, 0),
+    (50000, 65536, 2, -128, 127, 1),        # fewer elements than streams
+    (140000, 70001, 1, -64, 63, 0),         # ragged last workgroup
+])
+def test_many_streams_encode_bit_exact(api, orc, n, S, K, lo, hi, kind):
+    """Latents with at least 65,536 streams (one wavefront per SIMD and
+    more), including fewer elements than streams and a ragged last
+    workgroup: bitstream and offsets equal the oracle's; a symbol outside
+    the support gives ERANGE, and a short output ENOSPC with the oracle's
+    offsets."""
+    rng = np.random.default_rng(n + K)
+    w, mu, sig = synth.random_params(rng, n, K)
+    sym = np.clip(np.rint(rng.normal(0, 6, size=n)), lo, hi).astype(np.int32)
+    sym[:2] = [lo, hi]
+    ocfg = orc.make_cfg(K, lo, hi, 16, S, kind)
+    st, obs, ooff = orc.encode(ocfg, sym, w, mu, sig)
+    assert st == orc.OK
+    bs, off, dec = gpu_roundtrip(api, api.make_cfg(K, lo, hi, 16, S, kind), sym, w, mu, sig)
+    assert np.array_equal(off, ooff)
+    assert np.array_equal(bs, obs)
+    assert np.array_equal(dec, sym)
+    cfg = api.make_cfg(K, lo, hi, 16, S, kind)
+    dw, dm, ds = dev(w), dev(mu), dev(sig)
+    offb = torch.empty(S + 1, dtype=torch.int64, device="cuda")
+    s2 = sym.copy()
+    s2[n // 2] = hi + 1
+    big = torch.empty(int(ooff[-1]) + 64, dtype=torch.int16, device="cuda")
+    assert api.encode_into(cfg, dev(s2), dw, dm, ds, big, offb) == api.ERANGE
+    small = torch.empty(int(ooff[-1]) - 1, dtype=torch.int16, device="cuda")
+    assert api.encode_into(cfg, dev(sym), dw, dm, ds, small, offb) == api.ENOSPC
+    assert np.array_equal(offb.cpu().numpy(), ooff)
+
+
 def test_error_codes_match_oracle(api, orc):
     rng = np.random.default_rng(5)
     n, K, S = 3000, 3, 37
