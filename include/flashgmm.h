@@ -322,6 +322,16 @@ int gmm_plan_destroy(gmm_plan* plan);
  * Output is identical for every choice. GMM_EINVAL otherwise. */
 int gmm_set_decode_lanes(int32_t lanes);
 
+/* Issue priority, 0 (default) to 3, of the wavefronts of later
+ * gmm_encode / gmm_decode calls (subset passes and bracket decodes included;
+ * not the batched plans) made from the calling host thread. It matters only
+ * when kernels of several calls share the SIMDs (calls on different HIP
+ * streams): each SIMD issues the higher-priority wavefronts first, so
+ * latency-bound work of a low-priority call fills the issue slots that an
+ * issue-bound high-priority call leaves idle instead of taking its slots.
+ * Output is identical for every value. GMM_EINVAL outside 0..3. */
+int gmm_set_wave_priority(int32_t priority);
+
 /* Diagnostic: number of floats u in [2^-10, 2^10] on which the coder's fused
  * reciprocal differs from IEEE division (*count [host]); the library uses
  * the fused form on a device only when this is 0. Synchronous. */

@@ -75,6 +75,7 @@ _SIGS = {
     "gmm_fast_recip_mismatches": (ctypes.c_int, [_P, _P]),
     "gmm_params_from_raw": (ctypes.c_int, [_I32, _I64, _P, _P, _P, _P, _P]),
     "gmm_set_decode_lanes": (ctypes.c_int, [_I32]),
+    "gmm_set_wave_priority": (ctypes.c_int, [_I32]),
     "gmm_plan_create": (ctypes.c_int, [_CFG, _I32, _P, _P, _I32, _I32, _P]),
     "gmm_plan_exec": (ctypes.c_int, [_P, _P, _P, _P]),
     "gmm_plan_info": (ctypes.c_int, [_P, _P]),
@@ -268,6 +269,12 @@ def params_from_raw(logits, log_scales, stream=None):
 def set_decode_lanes(lanes: int) -> None:
     """Lanes per stream of later decodes (0 = automatic); output unchanged."""
     _check(lib().gmm_set_decode_lanes(int(lanes)), "set_decode_lanes")
+
+
+def set_wave_priority(priority: int) -> None:
+    """Wavefront issue priority (0..3) of this thread's later encode and
+    decode calls; output unchanged."""
+    _check(lib().gmm_set_wave_priority(int(priority)), "set_wave_priority")
 
 
 def fast_recip_mismatches() -> int:

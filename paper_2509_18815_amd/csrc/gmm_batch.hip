@@ -591,6 +591,7 @@ int gmm_plan_create(const gmm_cfg* common, int32_t B, const int64_t* n_b, const 
   p->B = B;
   p->flags = flags;
   p->q = make_qcfg(&c);
+  p->q.prio = 0;  // the batched kernels run at the default priority
   p->n.assign(n_b, n_b + B);
   p->S.assign(S_b, S_b + B);
   int dev = 0;

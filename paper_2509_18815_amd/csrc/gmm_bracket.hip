@@ -58,6 +58,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
                      const float* __restrict__ sg, int32_t* __restrict__ sym, uint32_t* status,
                      const BracketDev* __restrict__ br, unsigned long long* stats,
                      int32_t* dev_status) {
+  set_wave_priority(q.prio);
   __shared__ BracketLds lds;
   LaneModel model;
   load_lane_model(br, model, lds);
@@ -77,6 +78,7 @@ __global__ void __launch_bounds__(256)
                            const float* __restrict__ sg, int32_t* __restrict__ sym,
                            uint32_t* status, const BracketDev* __restrict__ br,
                            unsigned long long* stats, int32_t* dev_status) {
+  set_wave_priority(q.prio);
   const int64_t s0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64 * (64 / LG);
   if (s0 < S) {  // whole wavefronts
     GroupModel gm;

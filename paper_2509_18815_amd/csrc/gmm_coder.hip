@@ -185,8 +185,13 @@ int check_cfg(const gmm_cfg* c, int64_t n) {
   return GMM_OK;
 }
 
+// Wavefront priority of this host thread's later encode and decode launches
+// (gmm_set_wave_priority).
+thread_local int32_t g_wave_priority = 0;
+
 QCfg make_qcfg(const gmm_cfg* c) {
   QCfg q;
+  q.prio = g_wave_priority;
   q.lo = c->lo;
   q.N = c->hi - c->lo + 1;
   q.M = 1u << c->precision;
@@ -385,6 +390,12 @@ int gmm_set_decode_lanes(int32_t lanes) {
   return GMM_OK;
 }
 
+
+int gmm_set_wave_priority(int32_t priority) {
+  if (priority < 0 || priority > 3) return GMM_EINVAL;
+  fgmm::g_wave_priority = priority;
+  return GMM_OK;
+}
 
 const char* gmm_status_str(int s) {
   switch (s) {

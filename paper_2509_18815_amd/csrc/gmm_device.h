@@ -257,7 +257,20 @@ struct QCfg {
   float span;      // (float)(M - N)
   float lo_mh;     // (float)lo - 0.5, exact (|lo| <= 2^22)
   int32_t raw;     // 1: parameter planes hold raw outputs (weight logits, log-scales)
+  int32_t prio;    // issue priority of the launch's wavefronts, 0..3
 };
+
+// Raises the calling wavefront's issue priority (s_setprio) to p in 1..3;
+// 0 leaves the default. Among wavefronts sharing a SIMD the arbiter issues
+// the higher-priority ones first; results do not depend on it.
+__device__ __forceinline__ void set_wave_priority(int32_t p) {
+  if (p >= 3)
+    __builtin_amdgcn_s_setprio(3);
+  else if (p == 2)
+    __builtin_amdgcn_s_setprio(2);
+  else if (p == 1)
+    __builtin_amdgcn_s_setprio(1);
+}
 
 // Raw outputs of one element to weights and scales, in place: softmax of
 // the logits (differences to the largest, in component order, floored at

@@ -56,6 +56,7 @@ __global__ void k_enc_cdf(fgmm::QCfg q, int64_t n, const int32_t* __restrict__ s
                           uint32_t* status, const int32_t* __restrict__ idx = nullptr,
                           int64_t n_total = 0) {
   using namespace fgmm;
+  set_wave_priority(q.prio);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (kGather)
@@ -79,6 +80,7 @@ __global__ void __launch_bounds__(256)
              int32_t* dev_status, const int32_t* __restrict__ idx = nullptr,
              int64_t n_total = 0) {
   using namespace fgmm;
+  set_wave_priority(q.prio);
   const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t s = gt / L;
   const int g = (int)(gt % L);

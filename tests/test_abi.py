@@ -36,3 +36,6 @@ def test_host_side_queries_without_gpu():
     assert api.workspace_bytes(cfg, 49152, 0) > 49152 * 4
     bad = api.make_cfg(3, -128, 127, 7, 256)   # N > M/2
     assert L.gmm_workspace_bytes(ctypes.byref(bad), 10, 0) == -1
+    # launch settings are host state: checked without a GPU
+    assert L.gmm_set_wave_priority(4) == api.EINVAL and L.gmm_set_wave_priority(-1) == api.EINVAL
+    assert L.gmm_set_wave_priority(3) == api.OK and L.gmm_set_wave_priority(0) == api.OK

@@ -296,7 +296,8 @@ def test_two_streams_concurrent_bit_exact(api, orc):
     synchronisation in between, as the benchmark step runs them: every
     bitstream, offset table and decoded symbol equals the oracle's, and every
     status is OK. One latent has few streams (32 lanes per stream in
-    decode), the other 65,536 (one lane per stream)."""
+    decode), the other 65,536 (one lane per stream). Repeated with the
+    wavefront priorities set per stream as the benchmark step sets them."""
     rng = np.random.default_rng(21)
     cases = [(30000, 3, -255, 255, 256), (300000, 3, -255, 255, 65536)]
     main = torch.cuda.current_stream()
@@ -318,21 +319,33 @@ def test_two_streams_concurrent_bit_exact(api, orc):
              "st": torch.full((2,), -1, dtype=torch.int32, device="cuda")}
         work.append((cfg, t, sym, obs, ooff))
 
-    def chain(cfg, t):
+    def chain(cfg, t, prio):
+        api.set_wave_priority(prio)
         assert api.encode_into(cfg, t["sym"], t["w"], t["mu"], t["sig"], t["bs"], t["off"],
                                ws=t["wse"], status=t["st"][0:1]) == api.OK
         assert api.decode_into(cfg, t["bs"], t["off"], t["w"], t["mu"], t["sig"], t["dec"],
                                ws=t["wsd"], status=t["st"][1:2]) == api.OK
-    torch.cuda.synchronize()
-    for _ in range(4):
-        side.wait_stream(main)
-        with torch.cuda.stream(side):
-            chain(*work[0][:2])
-        chain(*work[1][:2])
-        main.wait_stream(side)
-    torch.cuda.synchronize()
-    for cfg, t, sym, obs, ooff in work:
-        assert t["st"].tolist() == [api.OK, api.OK]
-        assert np.array_equal(t["off"].cpu().numpy(), ooff)
-        assert np.array_equal(u16(t["bs"])[: ooff[-1]], obs)
-        assert np.array_equal(t["dec"].cpu().numpy(), sym)
+    try:
+        # wavefront priorities as in the benchmark step (none, then 3 on the
+        # many-stream latent, then the reverse): results never change
+        for p_side, p_main in [(0, 0), (0, 3), (3, 1)]:
+            for _, t, _, _, _ in work:
+                t["st"].fill_(-1)
+                t["dec"].fill_(0)
+            torch.cuda.synchronize()
+            for _ in range(4):
+                side.wait_stream(main)
+                with torch.cuda.stream(side):
+                    chain(*work[0][:2], p_side)
+                chain(*work[1][:2], p_main)
+                main.wait_stream(side)
+            torch.cuda.synchronize()
+            for cfg, t, sym, obs, ooff in work:
+                assert t["st"].tolist() == [api.OK, api.OK]
+                assert np.array_equal(t["off"].cpu().numpy(), ooff)
+                assert np.array_equal(u16(t["bs"])[: ooff[-1]], obs)
+                assert np.array_equal(t["dec"].cpu().numpy(), sym)
+    finally:
+        api.set_wave_priority(0)
+    with pytest.raises(api.GmmError):
+        api.set_wave_priority(4)
