@@ -58,6 +58,7 @@ def lib():
             "gmm_oracle_phi": (ctypes.c_float, [ctypes.c_float, i32]),
             "gmm_oracle_exp": (ctypes.c_float, [ctypes.c_float]),
             "gmm_oracle_as_tail": (ctypes.c_double, [ctypes.c_float]),
+            "gmm_oracle_as_constants": (None, [P]),
             "gmm_oracle_as_half": (ctypes.c_float, [ctypes.c_float, ctypes.c_float]),
             "gmm_oracle_phi_batch": (None, [P, P, i64, i32]),
             "gmm_oracle_exp_batch": (None, [P, P, i64]),
@@ -114,6 +115,13 @@ def as_tail(a) -> np.ndarray:
     a = np.asarray(a, dtype=np.float32).ravel()
     f = lib().gmm_oracle_as_tail
     return np.array([f(float(v)) for v in a], dtype=np.float64)
+
+
+def as_constants() -> np.ndarray:
+    """Kind 0's constants: 9p, 1/9, 81 log2(e)/2, density coefficients 0..5."""
+    out = np.zeros(9, dtype=np.float32)
+    lib().gmm_oracle_as_constants(_p(out))
+    return out
 
 
 def as_half(d, rn) -> np.ndarray:

@@ -154,6 +154,15 @@ double gmm_oracle_as_tail(float a) {
   return (double)dens * (double)q;
 }
 
+/* The kind-0 constants, for the tests that pin them to their definitions:
+ * out[0..8] = 9p, 1/9, 81 log2(e)/2, then the density coefficients 0..5. */
+void gmm_oracle_as_constants(float* out) {
+  out[0] = AS_P9;
+  out[1] = INV_NINE;
+  out[2] = AS_X;
+  for (int k = 0; k < 6; ++k) out[3 + k] = DENS_T[k];
+}
+
 /* One component's contribution Phi~(z) - 1/2 to the kind-0 mixture, from
  * d = b - mu and rn = r/9: a = min(|d| rn, 1); D = 1/2 - T rounded once
  * (a fused multiply-add of the two factors) and floored at 0 (the tail

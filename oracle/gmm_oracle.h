@@ -40,6 +40,8 @@ float gmm_oracle_phi(float z, int32_t kind);
  * product of its two binary32 factors), and one component's signed half
  * Phi~ - 1/2 from d = b - mu and rn = r/9. */
 double gmm_oracle_as_tail(float a);
+/* out[0..8]: 9p, 1/9, 81 log2(e)/2 and the six density coefficients. */
+void gmm_oracle_as_constants(float* out);
 float gmm_oracle_as_half(float d, float rn);
 /* exp~(g) for g in [-51.6, 7]: Cody-Waite reduction + degree-7 Taylor. */
 float gmm_oracle_exp(float g);

@@ -226,6 +226,25 @@ def test_many_streams_encode_bit_exact(api, orc, n, S, K, lo, hi, kind):
     assert np.array_equal(offb.cpu().numpy(), ooff)
 
 
+def test_4k_latent_whole_bitstream_equals_oracle(api, orc):
+    """The whole 320x135x240 latent at the benchmark's size and launch
+    shape (65,536 streams, one lane per stream): every offset and every word
+    of the GPU bitstream equals the oracle's (the oracle encodes all
+    10,368,000 symbols with its table method, some 30 s of host work), and
+    the GPU decodes it back to the symbols."""
+    cfgd = synth.CONFIGS["c2b"]
+    lat = synth.make_latents(cfgd)[0]
+    S = lat.streams
+    ocfg = orc.make_cfg(cfgd.K, cfgd.lo, cfgd.hi, cfgd.precision, S)
+    st, obs, ooff = orc.encode(ocfg, lat.symbols, lat.weights, lat.means, lat.scales)
+    assert st == orc.OK
+    bs, off, dec = gpu_roundtrip(api, api.make_cfg(cfgd.K, cfgd.lo, cfgd.hi, cfgd.precision, S),
+                                 lat.symbols, lat.weights, lat.means, lat.scales)
+    assert np.array_equal(off, ooff)
+    assert np.array_equal(bs, obs)
+    assert np.array_equal(dec, lat.symbols)
+
+
 def test_error_codes_match_oracle(api, orc):
     rng = np.random.default_rng(5)
     n, K, S = 3000, 3, 37

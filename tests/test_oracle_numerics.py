@@ -58,9 +58,12 @@ def test_phi_reflection_and_clamp(orc):
         hi = orc.phi(a, kind).astype(np.float64)
         # Phi(-a) + Phi(a) = 1 up to float rounding of 1 - tail
         assert np.abs(lo + hi - 1.0).max() <= 2.0 ** -24
-        # beyond |z| = 9 the value is the clamped one
+        # beyond |z| = 9 the value is the clamped one, however far
         big = a > 9.0
         assert np.all(lo[big] == orc.phi(np.float32([-9.0]), kind)[0])
+        far = np.float32([20.0, 1e4, 1e20, 3e38])
+        assert np.all(orc.phi(-far, kind) == orc.phi(np.float32([-9.0]), kind)[0])
+        assert np.all(orc.phi(far, kind) == orc.phi(np.float32([9.0]), kind)[0])
 
 
 def test_phi_non_decreasing_on_sorted_floats(orc):
@@ -183,6 +186,47 @@ def test_as_tail_against_binary64_approximant(orc):
     h = orc.as_half(d, np.float32(0.25)).astype(np.float64)
     assert np.all(np.sign(h[d != 0]) == np.sign(d[d != 0])) and h[3] == 0.0
     assert np.all(np.abs(h) <= 0.5) and abs(h[0]) == abs(h[-1])   # both clamped at a = 1
+
+
+def _nearest_f32(x):
+    """The binary32 nearest the Decimal x (ties: the even one)."""
+    from decimal import Decimal
+    f = np.float32(float(x))
+    cands = [np.nextafter(f, np.float32(-np.inf)), f, np.nextafter(f, np.float32(np.inf))]
+    return min(cands, key=lambda c: (abs(Decimal(float(c)) - x),
+                                      int(np.float32(c).view(np.uint32)) & 1))
+
+
+def test_as_constants_are_their_definitions(orc):
+    """Kind 0's constants against their definitions, computed here in
+    50-digit decimal arithmetic: 9 p with the handbook's p, 1/9,
+    81 log2(e)/2, and the density polynomial: the degree-7 Taylor
+    polynomial of C 2^(-g) (c_k = C (-ln 2)^k / k!, C = 1/sqrt(2 pi)) with
+    g^7 and g^6 replaced by their Chebyshev expansions on [-1/2, 1/2] less
+    the T7(2g)/8192 and T6(2g)/2048 terms (the expansions are checked here
+    too). Each constant must be the binary32 nearest its real."""
+    import math
+    from decimal import Decimal, getcontext
+    getcontext().prec = 50
+    pi = Decimal("3.14159265358979323846264338327950288419716939937510")
+    ln2 = Decimal(2).ln()
+    C = 1 / (2 * pi).sqrt()
+    c = [C * (-ln2) ** k / math.factorial(k) for k in range(8)]
+    # g^7 = T7(2g)/8192 + (7/16) g^5 - (7/128) g^3 + (7/4096) g and
+    # g^6 = T6(2g)/2048 + (3/8) g^4 - (9/256) g^2 + 1/2048 on [-1/2, 1/2]
+    g = np.linspace(-0.5, 0.5, 1001)
+    x = 2 * g
+    t7 = 64 * x ** 7 - 112 * x ** 5 + 56 * x ** 3 - 7 * x
+    t6 = 32 * x ** 6 - 48 * x ** 4 + 18 * x ** 2 - 1
+    assert np.abs(g ** 7 - (t7 / 8192 + 7 / 16 * g ** 5 - 7 / 128 * g ** 3 + 7 / 4096 * g)).max() < 1e-15
+    assert np.abs(g ** 6 - (t6 / 2048 + 3 / 8 * g ** 4 - 9 / 256 * g ** 2 + 1 / 2048)).max() < 1e-15
+    D = Decimal
+    dens = [c[0] + c[6] / 2048, c[1] + c[7] * D(7) / 4096, c[2] - c[6] * D(9) / 256,
+            c[3] - c[7] * D(7) / 128, c[4] + c[6] * D(3) / 8, c[5] + c[7] * D(7) / 16]
+    want = [9 * D("0.2316419"), 1 / D(9), 81 / (2 * ln2)] + dens
+    got = orc.as_constants()
+    for i, (gv, wv) in enumerate(zip(got, want)):
+        assert gv == _nearest_f32(wv), (i, float(gv), float(wv))
 
 
 def test_monotonicity_lemma_exhaustive_logistic(orc):
