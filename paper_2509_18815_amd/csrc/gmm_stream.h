@@ -109,16 +109,55 @@ __device__ __forceinline__ int32_t search_bs(const Elem<K>& e, const QCfg& q, in
   return lo;
 }
 
+// Maximum / minimum over the 16 lanes of a DPP row (every lane receives
+// it): rotations of the row by 1, 2, 4 and 8 lanes.
+__device__ __forceinline__ int32_t row16_max(int32_t v) {
+  v = max(v, __builtin_amdgcn_mov_dpp(v, 0x121, 0xF, 0xF, true));  // row_ror:1
+  v = max(v, __builtin_amdgcn_mov_dpp(v, 0x122, 0xF, 0xF, true));  // row_ror:2
+  v = max(v, __builtin_amdgcn_mov_dpp(v, 0x124, 0xF, 0xF, true));  // row_ror:4
+  v = max(v, __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, true));  // row_ror:8
+  return v;
+}
+__device__ __forceinline__ int32_t row16_min(int32_t v) {
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x121, 0xF, 0xF, true));
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x122, 0xF, 0xF, true));
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x124, 0xF, 0xF, true));
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, true));
+  return v;
+}
+
 // (L+1)-ary search by a group of L lanes (lane g of the group, group mask
 // gmask, first lane gbase): each round the lanes evaluate the CDF at L split
-// points of [lo, hi); a ballot counts the points at or below the slot and the
-// interval shrinks to one of the L+1 parts. The split points are
-// non-decreasing in g and below hi, so the count selects the right part.
+// points of [lo, hi); the interval shrinks to the part between the last
+// point at or below the slot and the first one above it. The split points
+// are non-decreasing in g and below hi, so the points at or below the slot
+// are a prefix of the group. With 16 lanes (a group is a DPP row) the new
+// bounds are row maxima and minima (lo' = max over lanes of (at or below ?
+// m : lo), hi' = min of (at or below ? hi : m), and the same for the CDF
+// values), which needs no LDS round trip; otherwise a ballot counts the
+// points at or below the slot and shuffles fetch the bounds.
 template <int K, int kKind, bool kFast, int L>
 __device__ __forceinline__ int32_t search_group(const Elem<K>& e, const QCfg& q, int rounds,
                                                 uint32_t slot, int g, int gbase, uint64_t gmask,
                                                 int32_t lo, int32_t hi, uint32_t& c_lo,
                                                 uint32_t& c_hi) {
+  if constexpr (L == 16) {
+    for (int r = 0; r < rounds; ++r) {
+      const uint32_t sz = (uint32_t)(hi - lo);
+      const int32_t m = lo + (int32_t)((sz * (uint32_t)(g + 1)) / (uint32_t)(L + 1));
+      const uint32_t c = cdf_lower<K, kKind, kFast>(e, q, m);  // m < hi <= N
+      const bool le = slot >= c;
+      const int32_t nlo = row16_max(le ? m : lo);
+      const int32_t nclo = row16_max((int32_t)(le ? c : c_lo));
+      const int32_t nhi = row16_min(le ? hi : m);
+      const int32_t nchi = row16_min((int32_t)(le ? c_hi : c));
+      lo = nlo;
+      hi = nhi;
+      c_lo = (uint32_t)nclo;
+      c_hi = (uint32_t)nchi;
+    }
+    return lo;
+  }
   for (int r = 0; r < rounds; ++r) {
     const uint32_t sz = (uint32_t)(hi - lo);
     const int32_t m = lo + (int32_t)((sz * (uint32_t)(g + 1)) / (uint32_t)(L + 1));
