@@ -314,7 +314,8 @@ int gmm_plan_destroy(gmm_plan* plan);
  * sequential rounds to ceil(log_{lanes+1} N) at the cost of more total
  * evaluations (for latents with few streams); 0 (default) chooses from the
  * stream count: the smallest power of two up to 32 that gives at least
- * 65,536 lanes. With a bracket, 16 or more lanes select the group form
+ * 65,536 lanes, except that 16 replaces 32 when it needs no more rounds
+ * (without a bracket). With a bracket, 16 or more lanes select the group form
  * with 16 lanes per stream (the network's prediction seeds one round that
  * evaluates 16 consecutive boundaries, with a 17-ary search as fallback),
  * 8 lanes the group form with 8 (8 boundaries, 9-ary fallback), fewer the
