@@ -445,23 +445,33 @@ def learned_step_form(api, lats, model, step, steps, warmup, plain_value, dev):
         r = api.decode_into(L.cfg, L.bs, L.off, L.lat.weights, L.lat.means, L.lat.scales, L.dec,
                             bracket=br, stats=stats, ws=L.ws_dec, status=L.st[1:2])
         assert r == 0
-    for _ in range(warmup):
-        step(kodak_decode=kodak_decode)
-    torch.cuda.synchronize()
-    stats.zero_()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step(kodak_decode=kodak_decode)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    def timed(kd):
+        # same procedure as the headline measurement: warm-up steps straight
+        # into the synchronisation that opens the timed region
+        for _ in range(warmup):
+            step(kodak_decode=kd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step(kodak_decode=kd)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    # plain and learned steps alternately, so both see the same conditions
+    plain_t, learned_t = [], []
+    for _ in range(2):
+        plain_t.append(timed(None))
+        stats.zero_()
+        learned_t.append(timed(kodak_decode))
     for nm in lats:
         lats[nm].verify()
     hits, misses, _, _ = stats.cpu().tolist()
     br.close()
     n_total = sum(lats[nm].n for nm in lats)
-    v = n_total * steps / elapsed
-    return {"value": v, "unit": "symbols/s", "ms_per_step": elapsed / steps * 1e3,
-            "gain_vs_plain_step": v / plain_value,
+    v = n_total * steps / (sum(learned_t) / 2)
+    vp = n_total * steps / (sum(plain_t) / 2)
+    return {"value": v, "unit": "symbols/s", "ms_per_step": sum(learned_t) / 2 / steps * 1e3,
+            "plain_step_value_here": vp, "gain_vs_plain_step": v / vp,
             "kodak_latent_hit_rate": hits / max(hits + misses, 1)}
 
 
@@ -572,8 +582,8 @@ def main():
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="c3,c4,c5,table2,epilogue",
                     help="comma list of extra forms measured after the timed steps: c3 batch "
@@ -633,11 +643,12 @@ def main():
             lats["c2b"].decode()
         stream.wait_stream(side)
 
+    # warm-up steps run back to back into the timed region's synchronisation
+    # (their outputs are checked with the timed ones: a check here would
+    # leave the device idle for milliseconds, after which the first timed
+    # steps were measured to run ~10% slower)
     for _ in range(args.warmup):
         step()
-    torch.cuda.synchronize()
-    for nm in names:
-        lats[nm].verify()
 
     # timed region: K steps, bracketed by device synchronisation
     torch.cuda.synchronize()
@@ -654,11 +665,13 @@ def main():
 
     # per-call times with HIP events on the launch stream (separate pass)
     ev = {}
-    reps = max(3, min(args.steps, 10))
+    reps = max(3, min(args.steps, 20))
     for nm in names:
         for op in ("encode", "decode"):
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)
+            for _ in range(reps):  # untimed calls first, back to back with the timed ones
+                getattr(lats[nm], op)()
             a.record(stream)
             for _ in range(reps):
                 getattr(lats[nm], op)()
