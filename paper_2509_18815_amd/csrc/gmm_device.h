@@ -347,26 +347,11 @@ __device__ __forceinline__ Elem<K> make_elem(const QCfg& q, const float (&rw)[K]
   return e;
 }
 
-// Quantized CDF c_j at boundary b_j = lo + j - 1/2 for j in [1, N-1]:
+// The scaled mixture y = RN(F (M - N)) at a boundary b (kinds 0..2):
 // F = sum_k w_k Phi~((b - mu_k) r_k) accumulated in component order with
-// fused multiply-adds, clamped to 1; c_j = j + floor(F (M - N)).
+// fused multiply-adds, clamped to [0, 1]. c_j = j + floor(y) at b = b_j.
 template <int K, int kKind, bool kFastRecip>
-__device__ __forceinline__ uint32_t cdf_inner(const Elem<K>& e, const QCfg& q, int32_t j) {
-  if constexpr (kKind == 3) {
-    // binary64 reference: z = (b - mu) / sigma, F and its quantization in binary64
-    const double b = (double)(q.lo + j) - 0.5;
-    double F = 0.0;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const double z = (b - (double)e.mu[k]) / (double)e.r[k];
-      F = __builtin_fma((double)e.w[k], phi_ref(z), F);
-    }
-    F = __builtin_fmin(F, 1.0);
-    return (uint32_t)j + (uint32_t)__builtin_floor(F * (double)(q.M - (uint32_t)q.N));
-  }
-  // (float)j + ((float)lo - 1/2) is the exact value lo + j - 1/2 (both
-  // terms and the sum are representable), i.e. the boundary b_j.
-  const float b = (float)j + q.lo_mh;
+__device__ __forceinline__ float cdf_scaled(const Elem<K>& e, const QCfg& q, float b) {
   float F = (kKind == 0) ? e.hw : 0.0f;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -381,8 +366,31 @@ __device__ __forceinline__ uint32_t cdf_inner(const Elem<K>& e, const QCfg& q, i
   // signed halves can round a few ulps below 0), folded into the last
   // fused multiply-add as its output modifier
   F = __builtin_fminf(__builtin_fmaxf(F, 0.0f), 1.0f);
-  // F >= 0 after the clamp, so the truncating conversion is the floor
-  return (uint32_t)j + (uint32_t)(F * q.span);
+  return F * q.span;
+}
+
+// Quantized CDF c_j at boundary b_j = lo + j - 1/2 for j in [1, N-1]:
+// c_j = j + floor(F (M - N)).
+template <int K, int kKind, bool kFastRecip>
+__device__ __forceinline__ uint32_t cdf_inner(const Elem<K>& e, const QCfg& q, int32_t j) {
+  if constexpr (kKind == 3) {
+    // binary64 reference: z = (b - mu) / sigma, F and its quantization in binary64
+    const double b = (double)(q.lo + j) - 0.5;
+    double F = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const double z = (b - (double)e.mu[k]) / (double)e.r[k];
+      F = __builtin_fma((double)e.w[k], phi_ref(z), F);
+    }
+    F = __builtin_fmin(F, 1.0);
+    return (uint32_t)j + (uint32_t)__builtin_floor(F * (double)(q.M - (uint32_t)q.N));
+  } else {
+    // (float)j + ((float)lo - 1/2) is the exact value lo + j - 1/2 (both
+    // terms and the sum are representable), i.e. the boundary b_j; the
+    // scaled value is >= 0, so the truncating conversion is the floor
+    const float b = (float)j + q.lo_mh;
+    return (uint32_t)j + (uint32_t)cdf_scaled<K, kKind, kFastRecip>(e, q, b);
+  }
 }
 
 // c_j for any j in [0, N] (c_0 = 0, c_N = M). The mixture is evaluated for

@@ -48,23 +48,39 @@ __device__ __forceinline__ int free_rounds(int rounds, int32_t N) {
 }
 
 // The same search with the round counts fixed at compile time: the rounds
-// are straight-line code (no loop counters or back-edges between them).
+// are straight-line code (no loop counters or back-edges between them), and
+// the interval is carried as the float boundary b_lo = lo + lo_mh instead of
+// the integer lo. Every value below is an integer or a half-integer of
+// magnitude < 2^23 (|lo| <= 2^22, slot < M <= 2^16), so each float sum and
+// difference is exact: b = b_lo + 2^r is b_mid, and s1 - b = slot + 1 - mid.
+// For an integer k and y >= 0, k >= floor(y) exactly when y < k + 1, so
+// slot >= c_mid = mid + floor(y) is the float test y < s1 - b: the same
+// decision as the integer form, without converting y or mid per round.
+// c_lo and c_hi are rebuilt at the end from the y of the rounds that set lo
+// and hi (initial y: 0 for c_0 = 0, M - 2^kRounds for c = M at 2^kRounds);
+// above N the contract's c_j = M is y = M - mid, which fails the test.
 template <int K, int kKind, bool kFast, int kRounds, int kFree>
 __device__ __forceinline__ int32_t search_fixed(const Elem<K>& e, const QCfg& q, uint32_t slot,
                                                 uint32_t& c_lo, uint32_t& c_hi) {
-  int32_t lo = 0;
-  c_lo = 0;
-  c_hi = q.M;
+  const float s1 = (float)(slot + 1u) + q.lo_mh;
+  const float bN = (float)q.N + q.lo_mh;
+  const float bM = (float)q.M + q.lo_mh;
+  float bl = q.lo_mh;
+  float yl = 0.0f;
+  float yh = (float)(q.M - (1u << kRounds));
 #pragma unroll
   for (int i = 0; i < kRounds; ++i) {
-    const int32_t mid = lo + (1 << (kRounds - 1 - i));
-    const uint32_t c = (i < kFree) ? cdf_inner<K, kKind, kFast>(e, q, mid)
-                                   : cdf_upper<K, kKind, kFast>(e, q, mid);
-    const bool right = slot >= c;
-    lo = right ? mid : lo;
-    c_lo = right ? c : c_lo;
-    c_hi = right ? c_hi : c;
+    const float b = bl + (float)(1 << (kRounds - 1 - i));
+    float y = cdf_scaled<K, kKind, kFast>(e, q, b);
+    if (i >= kFree) y = (b < bN) ? y : bM - b;
+    const bool right = y < s1 - b;
+    bl = right ? b : bl;
+    yl = right ? y : yl;
+    yh = right ? yh : y;
   }
+  const int32_t lo = (int32_t)(bl - q.lo_mh);
+  c_lo = (uint32_t)lo + (uint32_t)yl;
+  c_hi = (uint32_t)(lo + 1) + (uint32_t)yh;
   return lo;
 }
 
