@@ -98,6 +98,8 @@ CASES = [  # (n, S, K, lo, hi, P, kind)
     (4099, 256, 3, -128, 127, 16, 1),
     (70001, 300, 5, -511, 511, 16, 0),
     (20000, 257, 8, -64, 63, 14, 0),
+    (30000, 64, 3, -32, 31, 12, 0),  # binary32 quotient, largest quotients (< 2^20)
+    (30000, 64, 2, -16, 15, 11, 0),  # binary64 quotient
     (33333, 1000, 4, -255, 255, 16, 1),
 ]
 
