@@ -74,9 +74,9 @@ def lib():
             "gmm_oracle_ref_batch": (None, [P, P, i64, i32]),
             "gmm_oracle_params_from_raw": (ctypes.c_int, [i32, i64, P, P, P, P]),
             "gmm_oracle_mlp_num_params": (i64, [i32, i32]),
-            "gmm_oracle_mlp_forward": (None, [i32, i32, P, i64, P, P]),
+            "gmm_oracle_mlp_forward": (None, [i32, i32, P, i64, P, i32, P]),
             "gmm_oracle_mlp_loss_grad": (ctypes.c_double, [i32, i32, P, i64, P, P,
-                                                           ctypes.c_double, P]),
+                                                           ctypes.c_double, i32, P]),
         }
         for name, (res, args) in sigs.items():
             f = getattr(L, name)
@@ -231,23 +231,27 @@ def mlp_num_params(D: int, H: int = 64) -> int:
     return int(lib().gmm_oracle_mlp_num_params(D, H))
 
 
-def mlp_forward(params, X, H: int = 64) -> np.ndarray:
-    """FP64 forward of the bracket MLP (parameter layout W1, b1, W2, b2, w3, b3)."""
+def mlp_forward(params, X, H: int = 64, round_act: bool = False) -> np.ndarray:
+    """FP64 forward of the bracket MLP (parameter layout W1, b1, W2, b2, w3, b3);
+    with round_act the first layer's activations are rounded to bfloat16."""
     X = np.ascontiguousarray(X, dtype=np.float64)
     p = np.ascontiguousarray(params, dtype=np.float64)
     n, D = X.shape
     assert p.size == mlp_num_params(D, H)
     out = np.empty(n, dtype=np.float64)
-    lib().gmm_oracle_mlp_forward(D, H, _p(p), n, _p(X), _p(out))
+    lib().gmm_oracle_mlp_forward(D, H, _p(p), n, _p(X), int(bool(round_act)), _p(out))
     return out
 
 
-def mlp_loss_grad(params, X, y, delta=1.0, H: int = 64):
-    """Sum of Huber losses and its FP64 gradient (same layout as params)."""
+def mlp_loss_grad(params, X, y, delta=1.0, H: int = 64, round_act: bool = False):
+    """Sum of Huber losses and its FP64 gradient (same layout as params);
+    with round_act the first layer's activations are rounded to bfloat16
+    and the gradient passes straight through the rounding."""
     X = np.ascontiguousarray(X, dtype=np.float64)
     y = np.ascontiguousarray(y, dtype=np.float64)
     p = np.ascontiguousarray(params, dtype=np.float64)
     n, D = X.shape
     g = np.empty_like(p)
-    loss = lib().gmm_oracle_mlp_loss_grad(D, H, _p(p), n, _p(X), _p(y), float(delta), _p(g))
+    loss = lib().gmm_oracle_mlp_loss_grad(D, H, _p(p), n, _p(X), _p(y), float(delta),
+                                          int(bool(round_act)), _p(g))
     return float(loss), g

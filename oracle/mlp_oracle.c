@@ -9,19 +9,38 @@
  * decoder's search, whose result is verified against the exact CDF.
  * Parameters are one flat array: W1 [H][D], b1 [H], W2 [H][H], b2 [H],
  * w3 [H], b3 [1]. Loss and gradients are sums over the samples.
+ *
+ * With round_act the first hidden layer's activations relu(W1 x + b1) are
+ * rounded to bfloat16 (the 8-significant-bit format the decoder's matrix
+ * cores read: the value rounded to binary32, then its low 16 bits rounded
+ * off to nearest, ties to even) before the second layer uses them, and the
+ * gradient passes through the rounding unchanged (straight-through): the
+ * mask of the first layer is still "pre-activation > 0".
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
+static double bf16_round(double v) {
+  float f = (float)v;
+  uint32_t b;
+  memcpy(&b, &f, 4);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  b &= 0xFFFF0000u;
+  memcpy(&f, &b, 4);
+  return (double)f;
+}
+
 static int64_t n_params(int D, int H) { return (int64_t)H * D + H + (int64_t)H * H + H + H + 1; }
 
 int64_t gmm_oracle_mlp_num_params(int32_t D, int32_t H) { return n_params(D, H); }
 
 /* Forward pass of one sample; fills the pre-activations z1, z2 (length H)
- * and returns the output. */
-static double forward1(int D, int H, const double* p, const double* x, double* z1, double* z2) {
+ * and the first layer's activations a1 (rounded with round_act), and
+ * returns the output. */
+static double forward1(int D, int H, const double* p, const double* x, int round_act, double* z1,
+                       double* a1, double* z2) {
   const double* W1 = p;
   const double* b1 = W1 + (int64_t)H * D;
   const double* W2 = b1 + H;
@@ -32,10 +51,12 @@ static double forward1(int D, int H, const double* p, const double* x, double* z
     double s = b1[h];
     for (int d = 0; d < D; ++d) s += W1[(int64_t)h * D + d] * x[d];
     z1[h] = s;
+    const double a = s > 0.0 ? s : 0.0;
+    a1[h] = round_act ? bf16_round(a) : a;
   }
   for (int h = 0; h < H; ++h) {
     double s = b2[h];
-    for (int k = 0; k < H; ++k) s += W2[(int64_t)h * H + k] * (z1[k] > 0.0 ? z1[k] : 0.0);
+    for (int k = 0; k < H; ++k) s += W2[(int64_t)h * H + k] * a1[k];
     z2[h] = s;
   }
   double out = b3;
@@ -44,16 +65,18 @@ static double forward1(int D, int H, const double* p, const double* x, double* z
 }
 
 void gmm_oracle_mlp_forward(int32_t D, int32_t H, const double* params, int64_t n,
-                            const double* X, double* out) {
-  double* z = (double*)malloc(sizeof(double) * 2 * (size_t)H);
-  for (int64_t i = 0; i < n; ++i) out[i] = forward1(D, H, params, X + i * D, z, z + H);
+                            const double* X, int32_t round_act, double* out) {
+  double* z = (double*)malloc(sizeof(double) * 3 * (size_t)H);
+  for (int64_t i = 0; i < n; ++i)
+    out[i] = forward1(D, H, params, X + i * D, round_act, z, z + H, z + 2 * H);
   free(z);
 }
 
 /* Sum over samples of the Huber loss of (out - y) and its gradient with
  * respect to every parameter (grad has the parameter layout). */
 double gmm_oracle_mlp_loss_grad(int32_t D, int32_t H, const double* params, int64_t n,
-                                const double* X, const double* y, double delta, double* grad) {
+                                const double* X, const double* y, double delta,
+                                int32_t round_act, double* grad) {
   const int64_t P = n_params(D, H);
   memset(grad, 0, sizeof(double) * (size_t)P);
   double* gW1 = grad;
@@ -64,12 +87,12 @@ double gmm_oracle_mlp_loss_grad(int32_t D, int32_t H, const double* params, int6
   double* gb3 = gw3 + H;
   const double* W2 = params + (int64_t)H * D + H;
   const double* w3 = W2 + (int64_t)H * H + H;
-  double* buf = (double*)malloc(sizeof(double) * 4 * (size_t)H);
-  double *z1 = buf, *z2 = buf + H, *d2 = buf + 2 * H, *d1 = buf + 3 * H;
+  double* buf = (double*)malloc(sizeof(double) * 5 * (size_t)H);
+  double *z1 = buf, *z2 = buf + H, *d2 = buf + 2 * H, *d1 = buf + 3 * H, *a1 = buf + 4 * H;
   double loss = 0.0;
   for (int64_t i = 0; i < n; ++i) {
     const double* x = X + i * D;
-    const double out = forward1(D, H, params, x, z1, z2);
+    const double out = forward1(D, H, params, x, round_act, z1, a1, z2);
     const double r = out - y[i];
     const double ar = fabs(r);
     loss += (ar <= delta) ? 0.5 * r * r : delta * (ar - 0.5 * delta);
@@ -82,7 +105,7 @@ double gmm_oracle_mlp_loss_grad(int32_t D, int32_t H, const double* params, int6
     }
     for (int h = 0; h < H; ++h) {
       gb2[h] += d2[h];
-      for (int k = 0; k < H; ++k) gW2[(int64_t)h * H + k] += d2[h] * (z1[k] > 0.0 ? z1[k] : 0.0);
+      for (int k = 0; k < H; ++k) gW2[(int64_t)h * H + k] += d2[h] * a1[k];
     }
     for (int k = 0; k < H; ++k) {
       double s = 0.0;

@@ -1,7 +1,8 @@
 """GPU tests of the learned search bracket and its training kernels.
 
-- MLP loss/gradients from the GPU kernels against the FP64 oracle (float32
-  activations: relative 1e-4; bfloat16 first-layer activations: 2e-2);
+- MLP loss/gradients from the GPU kernels against the FP64 oracle, element
+  by element (float32 activations; bfloat16 first-layer activations against
+  the oracle rounding them the same way);
 - forward, features and one Adam step against their definitions;
 - training on exact tuples lowers the loss and reaches a useful hit rate;
 - the decoder's matrix-core inference agrees with the float32 forward;
@@ -42,24 +43,57 @@ def rand_net(rng, D, orc, scale=0.3):
     return (rng.normal(0, scale, size=orc.mlp_num_params(D))).astype(np.float32)
 
 
+BLOCKS = ("W1", "b1", "W2", "b2", "w3", "b3")
+
+
+def _block_of(i, D, H=64):
+    edges = np.cumsum([H * D, H, H * H, H, H, 1])
+    b = int(np.searchsorted(edges, i, side="right"))
+    return BLOCKS[b], i - (edges[b - 1] if b else 0)
+
+
+def _check_elementwise(got, ref, rtol, atol_rms, D, what):
+    """|got - ref| <= rtol |ref| + atol_rms rms(ref) for every element; prints
+    the worst element (by its share of the allowance) and its block."""
+    allow = rtol * np.abs(ref) + atol_rms * np.sqrt(np.mean(ref * ref))
+    ratio = np.abs(got - ref) / allow
+    i = int(np.argmax(ratio))
+    blk, k = _block_of(i, D)
+    print(f"{what} D={D}: worst element {i} ({blk}[{k}]): gpu {got[i]:.9g} oracle {ref[i]:.9g}, "
+          f"{ratio[i]:.3f} of the allowance")
+    for b, (lo, hi) in zip(BLOCKS, zip(np.r_[0, np.cumsum([64 * D, 64, 4096, 64, 64])],
+                                       np.cumsum([64 * D, 64, 4096, 64, 64, 1]))):
+        assert ratio[lo:hi].max() <= 1.0, (what, b, int(lo + np.argmax(ratio[lo:hi])))
+
+
 @pytest.mark.parametrize("D", [10, 16])
 def test_mlp_gradients_match_oracle(api, orc, D):
+    """The training kernels' loss and gradients against the FP64 oracle,
+    element by element: with float32 activations every gradient element is
+    within 1e-4 |g| + 1e-6 rms(g) of the oracle's (binary32 accumulation of
+    3,000 samples, whose residuals can cancel); with bfloat16 first-layer
+    activations against the oracle that rounds them the same way, within
+    2e-3 |g| + 2e-5 rms(g) (an activation whose binary32 value lies within
+    a binary32 rounding of a bfloat16 tie may round the other way than the
+    binary64 one: about one in 40,000 activations, each moving its sample's
+    terms by 2^-8 relative)."""
     rng = np.random.default_rng(D)
     n = 3000
     p = rand_net(rng, D, orc)
     X = rng.normal(size=(n, D)).astype(np.float32)
     y = rng.normal(scale=2.0, size=n).astype(np.float32)
-    loss, g = orc.mlp_loss_grad(p.astype(np.float64), X.astype(np.float64),
-                                y.astype(np.float64), 1.0)
-    out = api.mlp_loss_grad(dev(X), dev(y), dev(p), 1.0, round_act=False).cpu().numpy()
     P = p.size
-    assert abs(out[P] - loss) <= 1e-5 * abs(loss)
-    assert np.linalg.norm(out[:P] - g) <= 1e-4 * np.linalg.norm(g)
-    outb = api.mlp_loss_grad(dev(X), dev(y), dev(p), 1.0, round_act=True).cpu().numpy()
-    assert np.linalg.norm(outb[:P] - g) <= 2e-2 * np.linalg.norm(g)
-    fwd = api.mlp_forward(dev(X), dev(p), round_act=False).cpu().numpy()
-    ref = orc.mlp_forward(p.astype(np.float64), X.astype(np.float64))
-    assert np.abs(fwd - ref).max() <= 1e-4 * max(1.0, np.abs(ref).max())
+    for round_act, rtol, atol in ((False, 1e-4, 1e-6), (True, 5e-4, 5e-6)):
+        loss, g = orc.mlp_loss_grad(p.astype(np.float64), X.astype(np.float64),
+                                    y.astype(np.float64), 1.0, round_act=round_act)
+        out = api.mlp_loss_grad(dev(X), dev(y), dev(p), 1.0,
+                                round_act=round_act).cpu().numpy().astype(np.float64)
+        assert abs(out[P] - loss) <= (1e-5 if not round_act else 1e-4) * abs(loss)
+        _check_elementwise(out[:P], g, rtol, atol, D,
+                           "bf16 activations" if round_act else "float32")
+        fwd = api.mlp_forward(dev(X), dev(p), round_act=round_act).cpu().numpy()
+        ref = orc.mlp_forward(p.astype(np.float64), X.astype(np.float64), round_act=round_act)
+        assert np.abs(fwd - ref).max() <= 1e-4 * max(1.0, np.abs(ref).max())
 
 
 def test_mlp_gradients_bit_reproducible(api):

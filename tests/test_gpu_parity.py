@@ -128,8 +128,11 @@ def test_decode_lanes_per_stream_bit_exact(api, orc, lanes):
     is not a power of the search arity."""
     rng = np.random.default_rng(lanes)
     try:
+        # (6007, 96, 5, -511, 511, 0) at one lane per stream is the
+        # straight-line ten-round search of the A&S kind (N = 1023)
         for n, S, K, lo, hi, kind in [(20011, 129, 3, -255, 255, 0), (5000, 64, 5, -511, 511, 1),
-                                      (777, 1000, 2, -3, 3, 0), (40000, 300, 1, -128, 127, 0)]:
+                                      (777, 1000, 2, -3, 3, 0), (40000, 300, 1, -128, 127, 0),
+                                      (6007, 96, 5, -511, 511, 0)]:
             w, mu, sig = synth.random_params(rng, n, K)
             sym = np.clip(np.rint(rng.normal(0, 6, size=n)), lo, hi).astype(np.int32)
             ocfg = orc.make_cfg(K, lo, hi, 16, S, kind)
