@@ -50,6 +50,8 @@ extern "C" {
 #define GMM_ENOSPC 4   /* bitstream capacity smaller than the encoded size */
 #define GMM_EDEVICE 5  /* a HIP runtime call failed */
 #define GMM_ENOMEM 6   /* workspace allocation failed */
+#define GMM_E2BIG 7    /* gmm_encode_noalloc: the call needs more workspace than
+                          GMM_NOALLOC_SCRATCH_BYTES */
 
 /* Coder configuration (format parameters: encoder and decoder must agree).
  *  K           mixture components, 1..8
@@ -118,6 +120,29 @@ int gmm_encode(const gmm_cfg* cfg, int64_t n, const int32_t* symbols, const floa
                const float* means, const float* scales, uint16_t* bitstream,
                int64_t capacity_words, int64_t* offsets, void* ws, int64_t ws_bytes,
                int32_t* dev_status, void* stream);
+
+/* Allocation-free encode, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): gmm_encode without the ws and ws_bytes arguments, with the
+ * same kernels, output and status codes; the workspace is a static device
+ * array of
+ * GMM_NOALLOC_SCRATCH_BYTES that each device holds from the library's first
+ * use on it until the process ends. The call allocates nothing (no
+ * hipMalloc, hipMallocAsync or hipFree). GMM_E2BIG, before any launch, if
+ * gmm_workspace_bytes(cfg, n, 0) exceeds GMM_NOALLOC_SCRATCH_BYTES (the
+ * 320x135x240 latent with 65,536 streams needs 63.1 MB and fits).
+ * Every call on a device shares that device's array: calls that overlap on
+ * one device (concurrent streams or host threads) race and must be ordered
+ * by the caller. The first call on a device (unless another entry point ran
+ * there before) also runs the library's one-time check of its fused
+ * reciprocal, which synchronizes the stream; under stream capture make one
+ * call before capturing and pass dev_status (the synchronous form waits on
+ * the stream). */
+#define GMM_NOALLOC_SCRATCH_BYTES (64LL << 20)
+int gmm_encode_noalloc(const gmm_cfg* cfg, int64_t n, const int32_t* symbols,
+                       const float* weights, const float* means, const float* scales,
+                       uint16_t* bitstream, int64_t capacity_words, int64_t* offsets,
+                       int32_t* dev_status, void* stream);
 
 /* Subset passes (the paper's two-pass Checkerboard context model, Sec. IV-A:
  * anchors are coded first, then the other elements with parameters that

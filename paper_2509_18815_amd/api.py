@@ -15,7 +15,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libflashgmm.so")
 
-OK, EINVAL, ERANGE, ECORRUPT, ENOSPC, EDEVICE, ENOMEM = range(7)
+OK, EINVAL, ERANGE, ECORRUPT, ENOSPC, EDEVICE, ENOMEM, E2BIG = range(8)
 
 
 class GmmError(RuntimeError):
@@ -70,6 +70,7 @@ _SIGS = {
     "gmm_cdf_table": (ctypes.c_int, [_CFG, _I64, _P, _P, _P, _P, _P]),
     "gmm_inverse_cdf": (ctypes.c_int, [_CFG, _I64, _P, _P, _P, _P, _P, _P]),
     "gmm_encode": (ctypes.c_int, [_CFG, _I64, _P, _P, _P, _P, _P, _I64, _P, _P, _I64, _P, _P]),
+    "gmm_encode_noalloc": (ctypes.c_int, [_CFG, _I64, _P, _P, _P, _P, _P, _I64, _P, _P, _P]),
     "gmm_decode": (ctypes.c_int, [_CFG, _I64, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _I64,
                                   _P, _P]),
     "gmm_fast_recip_mismatches": (ctypes.c_int, [_P, _P]),
@@ -202,6 +203,21 @@ def encode_into(cfg: Cfg, symbols, weights, means, scales, bitstream, offsets, w
                             _dev(offsets, torch.int64, "offsets"), _opt(ws, torch.uint8, "ws"),
                             ws.numel() if ws is not None else 0,
                             _opt(status, torch.int32, "status"), _stream(stream))
+
+
+def encode_noalloc_into(cfg: Cfg, symbols, weights, means, scales, bitstream, offsets,
+                       status=None, stream=None) -> int:
+    """gmm_encode_noalloc into caller buffers: the library allocates nothing
+    (its workspace is a static device array). With ``status`` asynchronous;
+    otherwise it returns the status."""
+    n = symbols.numel()
+    w, m, s = _params(weights, means, scales, cfg.K)
+    if offsets.numel() != cfg.num_streams + 1:
+        raise ValueError("offsets must hold num_streams + 1 entries")
+    return lib().gmm_encode_noalloc(ctypes.byref(cfg), n, _dev(symbols, torch.int32, "symbols"),
+                                    w, m, s, _dev(bitstream, torch.int16, "bitstream"),
+                                    bitstream.numel(), _dev(offsets, torch.int64, "offsets"),
+                                    _opt(status, torch.int32, "status"), _stream(stream))
 
 
 def decode_into(cfg: Cfg, bitstream, offsets, weights, means, scales, symbols, total_words=None,

@@ -212,9 +212,12 @@ int search_rounds(int32_t N) {
 static std::mutex g_init_mu;
 static int g_fast_ok[64];  // 0 unknown, 1 verified, -1 mismatch
 
-int fast_recip_mismatches(unsigned long long* count, hipStream_t st) {
-  unsigned long long* d = nullptr;
-  if (hipMallocAsync((void**)&d, sizeof(unsigned long long), st) != hipSuccess) return GMM_ENOMEM;
+// counter [device, nullable]: 8 bytes for the mismatch count; when NULL the
+// check allocates it on the stream.
+int fast_recip_mismatches(unsigned long long* count, hipStream_t st, void* counter) {
+  unsigned long long* d = (unsigned long long*)counter;
+  if (!d && hipMallocAsync((void**)&d, sizeof(unsigned long long), st) != hipSuccess)
+    return GMM_ENOMEM;
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t*)d, 0u, (int64_t)2);
   const uint32_t lo = 0x3a800000u;            // 2^-10
   const uint32_t cnt = 0x44800000u - lo + 1;  // every float in [2^-10, 2^10]
@@ -222,19 +225,19 @@ int fast_recip_mismatches(unsigned long long* count, hipStream_t st) {
   unsigned long long h = 0;
   hipError_t e1 = hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, st);
   hipError_t e2 = hipStreamSynchronize(st);
-  (void)hipFreeAsync(d, st);
+  if (!counter) (void)hipFreeAsync(d, st);
   if (e1 != hipSuccess || e2 != hipSuccess) return GMM_EDEVICE;
   *count = h;
   return GMM_OK;
 }
 
-bool use_fast_recip(hipStream_t st) {
+bool use_fast_recip(hipStream_t st, void* counter) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return false;
   std::lock_guard<std::mutex> lk(g_init_mu);
   if (g_fast_ok[dev] == 0) {
     unsigned long long mm = 1;
-    if (fast_recip_mismatches(&mm, st) != GMM_OK) return false;
+    if (fast_recip_mismatches(&mm, st, counter) != GMM_OK) return false;
     g_fast_ok[dev] = (mm == 0) ? 1 : -1;
   }
   return g_fast_ok[dev] == 1;
@@ -410,6 +413,7 @@ const char* gmm_status_str(int s) {
     case GMM_ENOSPC: return "bitstream capacity too small";
     case GMM_EDEVICE: return "HIP runtime error";
     case GMM_ENOMEM: return "out of device memory";
+    case GMM_E2BIG: return "input too large for the static workspace of the allocation-free entry point";
     default: return "unknown status";
   }
 }
@@ -619,7 +623,7 @@ int gmm_params_from_raw(int32_t K, int64_t n, const float* logits, const float* 
 int gmm_fast_recip_mismatches(uint64_t* count, void* stream) {
   if (!count) return GMM_EINVAL;
   unsigned long long c = 0;
-  int r = fgmm::fast_recip_mismatches(&c, (hipStream_t)stream);
+  int r = fgmm::fast_recip_mismatches(&c, (hipStream_t)stream, nullptr);
   *count = c;
   return r;
 }

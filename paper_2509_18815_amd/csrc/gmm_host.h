@@ -13,7 +13,11 @@ namespace fgmm {
 int check_cfg(const gmm_cfg* c, int64_t n);
 QCfg make_qcfg(const gmm_cfg* c);
 int search_rounds(int32_t N);
-bool use_fast_recip(hipStream_t st);
+// Whether the fused reciprocal equals IEEE division on this device (checked
+// once per device, exhaustively; counter: optional 8-byte device buffer for
+// the check, else it allocates one on the stream).
+bool use_fast_recip(hipStream_t st, void* counter = nullptr);
+int fast_recip_mismatches(unsigned long long* count, hipStream_t st, void* counter);
 int finish(uint32_t* bits, int32_t* dev_status, hipStream_t st);
 int64_t encode_ws_bytes(int64_t n, int64_t S);
 int encode_launch(const gmm_cfg* cfg, int64_t n, const int32_t* symbols, const float* w,
