@@ -113,7 +113,8 @@ int gmm_inverse_cdf(const gmm_cfg* cfg, int64_t n, const float* weights, const f
  * S+1]: segment s occupies words offsets[s] .. offsets[s+1]-1 and
  * offsets[S] is the encoded size. GMM_ERANGE if a symbol is outside
  * [lo, hi]; GMM_ENOSPC if offsets[S] > capacity_words (offsets are still
- * written, the bitstream is not). Bitstream layout per segment: the final
+ * written; no word at or beyond capacity_words is written, the words below
+ * it are unspecified). Bitstream layout per segment: the final
  * 32-bit state as two little-endian uint16 words, then the renormalisation
  * words in the order the decoder reads them. */
 int gmm_encode(const gmm_cfg* cfg, int64_t n, const int32_t* symbols, const float* weights,

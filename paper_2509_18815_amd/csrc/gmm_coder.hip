@@ -84,6 +84,60 @@ __global__ void __launch_bounds__(kRansBlock)
   }
 }
 
+// Encode phase 2 with the renormalisation words staged in LDS, in one pass:
+// a workgroup of 256 streams (taken in start order from a ticket counter,
+// bits[1]) runs the recurrence with each lane's emitted words in a column
+// of the dynamic LDS array words[cap][256], scans its segment lengths
+// (2 + count), gets the exclusive prefix of the words of all earlier
+// workgroups by decoupled look-back over slots[] (zeroed before the launch),
+// and writes its streams' offsets and, when its range fits the capacity,
+// their segments straight into the bitstream (each lane its own stream's;
+// a copy by whole wavefronts, 64 consecutive words per store, took longer
+// for its per-stream shuffles). The workgroup holding the last streams
+// writes offsets[S], flags ENOSPC and writes the call's status code
+// (bits[0]: status bits).
+__global__ void __launch_bounds__(kRansBlock)
+    k_enc_rans_lds(int64_t n, int64_t S, int P, const uint32_t* __restrict__ cf,
+                   int64_t* __restrict__ offsets, uint16_t* __restrict__ bitstream,
+                   int64_t capacity, uint64_t* slots, uint32_t* bits, int32_t* dev_status) {
+  extern __shared__ uint16_t words[];  // [cap][kRansBlock]
+  __shared__ int64_t ticket_sh, excl_sh;
+  if (threadIdx.x == 0) ticket_sh = (int64_t)atomicAdd(bits + 1, 1u);
+  __syncthreads();
+  const int64_t ticket = ticket_sh;
+  const int64_t s = ticket * kRansBlock + threadIdx.x;
+  uint32_t cnt = 0, x = 1u << 16;
+  if (s < S) x = rans_stream_lds(n, S, P, s, cf, words + threadIdx.x, kRansBlock, &cnt);
+  uint32_t tot;
+  const uint32_t len = (s < S) ? cnt + 2u : 0u;
+  const uint32_t local = block_excl_scan<kRansBlock>(len, &tot);
+  if (threadIdx.x < 64) {
+    const int64_t e = lookback_prefix(slots, ticket, (int64_t)tot);
+    if (threadIdx.x == 0) excl_sh = e;
+  }
+  __syncthreads();
+  const int64_t excl = excl_sh;
+  if (s < S) offsets[s] = excl + (int64_t)local;
+  const int64_t nblk = (S + kRansBlock - 1) / kRansBlock;
+  if (ticket == nblk - 1 && threadIdx.x == 0) {
+    const int64_t total = excl + (int64_t)tot;
+    offsets[S] = total;
+    const uint32_t nospace = (total > capacity) ? kStNoSpace : 0u;
+    const uint32_t b = atomicOr(bits, nospace) | nospace;
+    if (dev_status) *dev_status = status_code(b);
+  }
+  if (excl + (int64_t)tot > capacity) return;
+  // copy out: each lane writes its own stream's segment, the state words
+  // and then the renormalisation words in decoder order (newest first)
+  if (s < S) {
+    const int64_t o = excl + (int64_t)local;
+    bitstream[o] = (uint16_t)(x & 0xFFFFu);
+    bitstream[o + 1] = (uint16_t)(x >> 16);
+    const uint16_t* col = words + threadIdx.x;
+    for (uint32_t t = 0; t < cnt; ++t) bitstream[o + 2 + t] = col[(cnt - 1u - t) * kRansBlock];
+  }
+}
+
 // Offsets and compaction: 16 lanes per stream.
 constexpr int kPackBlock = 256, kPackLanes = 16;
 __global__ void __launch_bounds__(kPackBlock)
@@ -146,7 +200,7 @@ namespace {
 int64_t align256(int64_t b) { return (b + 255) & ~(int64_t)255; }
 
 struct EncLayout {
-  int64_t status, cf, scratch, xfin, count, local_off, blk_total, blk_pre, bytes;
+  int64_t status, look, cf, scratch, xfin, count, local_off, blk_total, blk_pre, bytes;
   int64_t cap, nblk;
 };
 
@@ -156,6 +210,7 @@ EncLayout enc_layout(int64_t n, int64_t S) {
   L.nblk = (S + kRansBlock - 1) / kRansBlock;
   int64_t o = 0;
   L.status = o; o += 256;
+  L.look = o; o += align256(8 * L.nblk);  // look-back slots, zeroed with the status words
   L.cf = o; o += align256(4 * n);
   L.scratch = o; o += align256(2 * S * L.cap);
   L.xfin = o; o += align256(4 * S);
@@ -258,6 +313,18 @@ int finish(uint32_t* bits, int32_t* dev_status, hipStream_t st) {
   return GMM_OK;
 }
 
+// Largest dynamic LDS of k_enc_rans_lds (words of a workgroup's streams):
+// streams of up to 300 symbols; longer ones take the scratch-row path.
+constexpr int64_t kRansLdsMax = 300 * kRansBlock * 2;
+
+// Lets k_enc_rans_lds use more than the default dynamic LDS (once).
+bool enc_lds_ready() {
+  static const bool ok = hipFuncSetAttribute((const void*)k_enc_rans_lds,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)kRansLdsMax) == hipSuccess;
+  return ok;
+}
+
 // Encode with an explicit workspace (used by the C entry point and plans).
 int encode_launch(const gmm_cfg* cfg, int64_t n, const int32_t* symbols, const float* w,
                   const float* mu, const float* sg, uint16_t* bitstream, int64_t capacity,
@@ -274,8 +341,11 @@ int encode_launch(const gmm_cfg* cfg, int64_t n, const int32_t* symbols, const f
   uint32_t* local_off = (uint32_t*)(ws + L.local_off);
   int64_t* blk_total = (int64_t*)(ws + L.blk_total);
   int64_t* blk_pre = (int64_t*)(ws + L.blk_pre);
-  // status bits and the workgroup counter of k_enc_rans
-  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, status, 0u, (int64_t)2);
+  // status bits, the workgroup counter (or ticket counter) of the rANS
+  // pass and the look-back slots
+  const int64_t nclear = (L.look + 8 * L.nblk) / 4;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((nclear + 255) / 256)), dim3(256), 0, st,
+                     status, 0u, nclear);
   if (n > 0) {
     const dim3 grid((unsigned)((n + 255) / 256)), block(256);
     if (idx) hipLaunchKernelGGL(k_check_idx, grid, block, 0, st, idx, n, n_total, status);
@@ -293,6 +363,14 @@ int encode_launch(const gmm_cfg* cfg, int64_t n, const int32_t* symbols, const f
                            mu, sg, cf, status, nullptr, (int64_t)0);
     });
   }
+  const int64_t lds = L.cap * kRansBlock * 2;
+  if (lds <= kRansLdsMax && enc_lds_ready()) {
+    hipLaunchKernelGGL(k_enc_rans_lds, dim3((unsigned)L.nblk), dim3(kRansBlock), (size_t)lds, st,
+                       n, S, cfg->precision, cf, offsets, bitstream, capacity,
+                       (uint64_t*)(ws + L.look), status, dev_status);
+    return hipGetLastError() == hipSuccess ? GMM_OK : GMM_EDEVICE;
+  }
+  // streams too long for LDS: words through the scratch rows, then k_pack
   hipLaunchKernelGGL(k_enc_rans, dim3((unsigned)L.nblk), dim3(kRansBlock), 0, st, n, S,
                      cfg->precision, cf, scratch, L.cap, xfin, count, local_off, blk_total,
                      blk_pre, capacity, status, dev_status);

@@ -222,6 +222,33 @@ __device__ __forceinline__ uint32_t enc_cdf_elem(const QCfg& q, int64_t n, int64
 // s_waitcnt immediate: vector memory count 0, the other counters unlimited.
 constexpr int kWaitVm0 = 0x0F70;
 
+// One encode step of the rANS recurrence for the packed word cfw = (c << 16)
+// | f: renormalise (emit = whether the low 16 bits of x, returned in word,
+// leave the state), then x <- (x div f) 2^P + (x mod f) + c (Eq. (3)).
+__device__ __forceinline__ void rans_put(uint32_t& x, uint32_t cfw, int P, int shift, bool& emit,
+                                         uint32_t& word) {
+  const uint32_t c = cfw >> 16;
+  const uint32_t f = cfw & 0xFFFFu;
+  // 1/f in binary64 off the chain: hardware estimate, one Newton step
+  const double fd = (double)f;
+  const double y0 = __builtin_amdgcn_rcp(fd);
+  const double rf = __builtin_fma(__builtin_fma(-fd, y0, 1.0), y0, y0);
+  emit = x >= (f << shift);
+  word = x & 0xFFFFu;
+  x = emit ? (x >> 16) : x;
+  // x <- (x div f) 2^P + (x mod f) + c, exactly: with rf within 2^-50 of
+  // 1/f, x rf is within 2^-17 of x / f < 2^32, while a non-integer
+  // x / f lies at least 1/f >= 2^-16 below the next integer, so
+  // q0 = trunc(x rf) is the quotient q or q - 1; then r0 = x - q0 f
+  // (exact) is the remainder or the remainder + f, and one comparison
+  // fixes both. Every binary64 value here is an integer below 2^53.
+  const double xd = (double)x;
+  const double q0 = __builtin_trunc(xd * rf);
+  const double r0 = __builtin_fma(-q0, fd, xd);
+  const double fix = (r0 >= fd) ? (double)((1u << P) - f) : 0.0;
+  x = (uint32_t)(__builtin_fma(q0, (double)(1u << P), r0 + (double)c) + fix);
+}
+
 // Encode phase 2 for stream s: the integer rANS recurrence over the packed
 // (c, f) words cf[s + p S], p = n_s-1 .. 0. The k-th emitted word goes to
 // region_end[-k], so the words end up in the order the decoder reads them.
@@ -277,28 +304,10 @@ __device__ __forceinline__ uint32_t rans_stream(int64_t n, int64_t S, int P, int
 #pragma unroll
     for (int d = 0; d < kDepth; ++d) {
       if (p - d < 0) break;
-      const uint32_t c = cur[d] >> 16;
-      const uint32_t f = cur[d] & 0xFFFFu;
-      // 1/f in binary64 off the chain: hardware estimate, one Newton step
-      const double fd = (double)f;
-      const double y0 = __builtin_amdgcn_rcp(fd);
-      const double rf = __builtin_fma(__builtin_fma(-fd, y0, 1.0), y0, y0);
-      const bool emit = x >= (f << shift);
-      pend[d] = x & 0xFFFFu;
+      bool emit;
+      rans_put(x, cur[d], P, shift, emit, pend[d]);
       pmask |= (emit ? 1u : 0u) << d;
       cnt += emit ? 1u : 0u;
-      x = emit ? (x >> 16) : x;
-      // x <- (x div f) 2^P + (x mod f) + c, exactly: with rf within 2^-50 of
-      // 1/f, x rf is within 2^-17 of x / f < 2^32, while a non-integer
-      // x / f lies at least 1/f >= 2^-16 below the next integer, so
-      // q0 = trunc(x rf) is the quotient q or q - 1; then r0 = x - q0 f
-      // (exact) is the remainder or the remainder + f, and one comparison
-      // fixes both. Every binary64 value here is an integer below 2^53.
-      const double xd = (double)x;
-      const double q0 = __builtin_trunc(xd * rf);
-      const double r0 = __builtin_fma(-q0, fd, xd);
-      const double fix = (r0 >= fd) ? (double)((1u << P) - f) : 0.0;
-      x = (uint32_t)(__builtin_fma(q0, (double)(1u << P), r0 + (double)c) + fix);
     }
   }
 #pragma unroll
@@ -308,6 +317,107 @@ __device__ __forceinline__ uint32_t rans_stream(int64_t n, int64_t S, int P, int
           (uint16_t)pend[d];
   *count = cnt;
   return x;
+}
+
+// Encode phase 2 for stream s with the emitted words kept in LDS: the k-th
+// emitted word goes to col[k stride] (a column of the workgroup's word
+// array, so that the lanes of a step write neighbouring LDS words). The
+// (c, f) words are loaded a block of kDepth steps ahead as in rans_stream;
+// the LDS stores do not count on the vector-memory counter, so the one wait
+// per block is for those loads only. Returns the final state; *count
+// receives the number of words (at most n_s).
+__device__ __forceinline__ uint32_t rans_stream_lds(int64_t n, int64_t S, int P, int64_t s,
+                                                    const uint32_t* __restrict__ cf,
+                                                    uint16_t* col, int stride, uint32_t* count) {
+  const int64_t ns = stream_len(n, S, s);
+  uint32_t x = 1u << 16;
+  uint32_t cnt = 0;
+  const int shift = 32 - P;
+  constexpr int kDepth = 8;
+  int64_t dS[kDepth];
+#pragma unroll
+  for (int d = 0; d < kDepth; ++d) dS[d] = (int64_t)d * S;
+  uint32_t buf[kDepth];
+  int64_t base = s + (ns - 1) * S;  // position ns - 1
+#pragma unroll
+  for (int d = 0; d < kDepth; ++d) buf[d] = (ns - 1 - d >= 0) ? cf[base - dS[d]] : 0u;
+  const int64_t step = (int64_t)kDepth * S;
+  for (int64_t p = ns - 1; p >= 0; p -= kDepth) {
+    base -= step;  // position p - kDepth
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
+    uint32_t cur[kDepth];
+#pragma unroll
+    for (int d = 0; d < kDepth; ++d) cur[d] = buf[d];
+#pragma unroll
+    for (int d = 0; d < kDepth; ++d) {
+      // unconditional (positions below 0 reload position 0)
+      const int64_t at = base - dS[d];
+      buf[d] = cf[at >= s ? at : s];
+    }
+#pragma unroll
+    for (int d = 0; d < kDepth; ++d) {
+      if (p - d < 0) break;
+      bool emit;
+      uint32_t word;
+      rans_put(x, cur[d], P, shift, emit, word);
+      if (emit) col[cnt * stride] = (uint16_t)word;
+      cnt += emit ? 1u : 0u;
+    }
+  }
+  *count = cnt;
+  return x;
+}
+
+// Sum of v over the 64 lanes of a wavefront (every lane receives it).
+__device__ __forceinline__ int64_t wave_sum64(int64_t v) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+// Decoupled look-back: the sum of the totals of every workgroup with a
+// smaller ticket (workgroups take tickets in the order they start, from an
+// atomic counter). slots[t] is 0 until workgroup t publishes (1 << 62) |
+// its total, and later (2 << 62) | its inclusive prefix; the slots are
+// zeroed before the launch. The ticket order guarantees that every
+// workgroup waited on has started, and a workgroup publishes its total
+// before it waits on anyone, so the waits end. Called by all 64 lanes of
+// one wavefront; every lane receives the result. The slots are read and
+// written with device-scope atomics (coherent across XCDs).
+constexpr uint64_t kLbAggregate = 1ull << 62, kLbInclusive = 2ull << 62;
+constexpr uint64_t kLbValue = (1ull << 62) - 1;
+__device__ __forceinline__ int64_t lookback_prefix(uint64_t* slots, int64_t ticket,
+                                                   int64_t total) {
+  const int lane = threadIdx.x & 63;
+  if (lane == 0)
+    __hip_atomic_store(&slots[ticket], kLbAggregate | (uint64_t)total, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  int64_t excl = 0;
+  int64_t j = ticket - 1;  // the newest slot not yet summed
+  while (j >= 0) {
+    // lane i looks at slot j - i; slots before 0 act as an inclusive 0
+    const int64_t k = j - lane;
+    const uint64_t v = (k >= 0) ? __hip_atomic_load(&slots[k], __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT)
+                                : kLbInclusive;
+    const uint64_t flag = v >> 62;
+    const uint64_t notready = __ballot(flag == 0);
+    const uint64_t incl = __ballot(flag == 2);
+    const int first_nr = notready ? __ffsll((long long)notready) - 1 : 64;
+    const int first_in = incl ? __ffsll((long long)incl) - 1 : 64;
+    if (first_in < first_nr) {  // lanes 0..first_in reach an inclusive prefix
+      excl += wave_sum64(lane <= first_in ? (int64_t)(v & kLbValue) : 0);
+      break;
+    }
+    // lanes 0..first_nr-1 hold totals: add them and look further back
+    excl += wave_sum64(lane < first_nr ? (int64_t)(v & kLbValue) : 0);
+    j -= first_nr;
+    if (first_nr == 0) __builtin_amdgcn_s_sleep(1);
+  }
+  if (lane == 0)
+    __hip_atomic_store(&slots[ticket], kLbInclusive | (uint64_t)(excl + total),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return excl;
 }
 
 // Inclusive prefix sum across the 64 lanes of a wavefront.

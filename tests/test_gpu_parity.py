@@ -267,11 +267,14 @@ def test_error_codes_match_oracle(api, orc):
     s2 = sym.copy()
     s2[1234] = 32
     assert api.encode_into(cfg, dev(s2), dw, dm, ds, bsb, offb) == api.ERANGE
-    # capacity: offsets written, equal to the oracle's
+    # capacity: offsets written, equal to the oracle's; nothing written at or
+    # beyond the capacity (a guard region after it keeps its words)
     st, obs, ooff = orc.encode(ocfg, sym, w, mu, sig)
-    small = torch.empty(int(ooff[-1]) - 1, dtype=torch.int16, device="cuda")
-    assert api.encode_into(cfg, dev(sym), dw, dm, ds, small, offb) == api.ENOSPC
+    cap = int(ooff[-1]) - 1
+    buf = torch.full((cap + 4096,), 0x5A5A, dtype=torch.int16, device="cuda")
+    assert api.encode_into(cfg, dev(sym), dw, dm, ds, buf[:cap], offb) == api.ENOSPC
     assert np.array_equal(offb.cpu().numpy(), ooff)
+    assert bool((buf[cap:] == 0x5A5A).all())
     # corrupted streams: same status and the same (deterministic) symbols
     dec = torch.empty(n, dtype=torch.int32, device="cuda")
     flipped = obs.copy()
