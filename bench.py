@@ -4,8 +4,9 @@ A step codes the paper-scale workload once: the Kodak-size latent
 (320x48x32, 4,096 streams) and the 4K latent (320x135x240, 65,536 streams),
 K = 3, support [-255, 255], P = 16 — each latent encoded, then decoded. The
 two latents are independent, so their chains run on two HIP streams (both
-at the default priority): the Kodak-size latent's latency-bound kernels
-fill issue slots that the 4K latent's kernels leave free. Inputs are
+at the default priority, each running its steps back to back): the
+Kodak-size latent's latency-bound kernels fill issue slots that the 4K
+latent's kernels leave free. Inputs are
 seeded synthetic latents resident in HBM before timing starts; every timed
 step's output is the bit-exact round trip (checked after timing).
 
@@ -626,8 +627,11 @@ def main():
 
     def step(record=False, kodak_decode=None):
         # the Kodak-size latent's chain on the side stream, the 4K latent's
-        # on the main stream; the step ends when both have finished
-        side.wait_stream(stream)
+        # on the main stream. The two chains are independent and are not
+        # joined step by step (a join per step was measured to leave the
+        # main stream idle ~16 us per step while the cross-stream wait
+        # resolved): each stream runs its steps back to back, and the timed
+        # region ends when both are idle.
         with torch.cuda.stream(side):
             lats["c2a"].encode()
             (kodak_decode or lats["c2a"].decode)()
@@ -641,12 +645,12 @@ def main():
             ev_pairs.append((a, b))
         else:
             lats["c2b"].decode()
-        stream.wait_stream(side)
 
     # warm-up steps run back to back into the timed region's synchronisation
     # (their outputs are checked with the timed ones: a check here would
     # leave the device idle for milliseconds, after which the first timed
     # steps were measured to run ~10% slower)
+    side.wait_stream(stream)  # the inputs were written on the main stream
     for _ in range(args.warmup):
         step()
 

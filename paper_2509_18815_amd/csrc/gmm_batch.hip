@@ -108,8 +108,9 @@ __global__ void __launch_bounds__(kRBlock)
     const int64_t gs = blk * kRBlock + threadIdx.x;
     uint32_t cnt = 0;
     if (s < d.S) {
+      bool zf;  // phase 1 of plans reports ranges itself and never writes f = 0
       xfin[gs] = rans_stream(d.n, d.S, P, s, cf + d.elem_base,
-                             scratch + d.scratch_base + s * d.cap + (d.cap - 1), &cnt);
+                             scratch + d.scratch_base + s * d.cap + (d.cap - 1), &cnt, &zf);
       count[gs] = cnt;
     }
     uint32_t tot;

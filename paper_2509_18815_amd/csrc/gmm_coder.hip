@@ -68,8 +68,10 @@ __global__ void __launch_bounds__(kRansBlock)
   const int64_t s = (int64_t)blockIdx.x * kRansBlock + threadIdx.x;
   uint32_t cnt = 0;
   if (s < S) {
-    xfin[s] = rans_stream(n, S, P, s, cf, scratch + s * cap + (cap - 1), &cnt);
+    bool zf;
+    xfin[s] = rans_stream(n, S, P, s, cf, scratch + s * cap + (cap - 1), &cnt, &zf);
     count[s] = cnt;
+    if (zf) atomicOr(bits, kStRange);  // an out-of-range symbol (phase 1 wrote f = 0)
   }
   uint32_t tot;
   const uint32_t excl = block_excl_scan<kRansBlock>((s < S) ? cnt + 2u : 0u, &tot);
@@ -107,10 +109,18 @@ __global__ void __launch_bounds__(kRansBlock)
   const int64_t ticket = ticket_sh;
   const int64_t s = ticket * kRansBlock + threadIdx.x;
   uint32_t cnt = 0, x = 1u << 16;
-  if (s < S) x = rans_stream_lds(n, S, P, s, cf, words + threadIdx.x, kRansBlock, &cnt);
+  bool zf = false;
+  if (s < S) x = rans_stream_lds(n, S, P, s, cf, words + threadIdx.x, kRansBlock, &cnt, &zf);
   uint32_t tot;
   const uint32_t len = (s < S) ? cnt + 2u : 0u;
   const uint32_t local = block_excl_scan<kRansBlock>(len, &tot);
+  // an out-of-range symbol (phase 1 wrote f = 0): the status bit is set,
+  // and complete, before this workgroup publishes its total, so the
+  // workgroup of the last streams sees it once its look-back has ended
+  if (__syncthreads_or(zf ? 1 : 0) && threadIdx.x == 0) {
+    atomicOr(bits, kStRange);
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
+  }
   if (threadIdx.x < 64) {
     const int64_t e = lookback_prefix(slots, ticket, (int64_t)tot);
     if (threadIdx.x == 0) excl_sh = e;
@@ -342,10 +352,14 @@ int encode_launch(const gmm_cfg* cfg, int64_t n, const int32_t* symbols, const f
   int64_t* blk_total = (int64_t*)(ws + L.blk_total);
   int64_t* blk_pre = (int64_t*)(ws + L.blk_pre);
   // status bits, the workgroup counter (or ticket counter) of the rANS
-  // pass and the look-back slots
+  // pass and the look-back slots: zeroed by the first workgroup of phase 1
+  // when phase 1 is the plain-kind, non-gather kernel (nothing before it
+  // writes them), else by a fill kernel first
   const int64_t nclear = (L.look + 8 * L.nblk) / 4;
-  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((nclear + 255) / 256)), dim3(256), 0, st,
-                     status, 0u, nclear);
+  const bool clear_in_cdf = n > 0 && !idx && cfg->cdf_kind < 2;
+  if (!clear_in_cdf)
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((nclear + 255) / 256)), dim3(256), 0, st,
+                       status, 0u, nclear);
   if (n > 0) {
     const dim3 grid((unsigned)((n + 255) / 256)), block(256);
     if (idx) hipLaunchKernelGGL(k_check_idx, grid, block, 0, st, idx, n, n_total, status);
@@ -360,7 +374,7 @@ int encode_launch(const gmm_cfg* cfg, int64_t n, const int32_t* symbols, const f
                            mu, sg, cf, status, idx, n_total);
       else
         hipLaunchKernelGGL((k_enc_cdf<K_, KI, F, false>), grid, block, 0, st, q, n, symbols, w,
-                           mu, sg, cf, status, nullptr, (int64_t)0);
+                           mu, sg, cf, status, nullptr, (int64_t)0, status, nclear);
     });
   }
   const int64_t lds = L.cap * kRansBlock * 2;

@@ -48,22 +48,28 @@ __global__ void k_inverse(fgmm::QCfg q, int rounds, int64_t n, const float* __re
 }
 
 // Encode phase 1: one thread per element (per pass position with kGather:
-// element idx[i] of a latent of n_total elements).
+// element idx[i] of a latent of n_total elements). An out-of-range symbol
+// gives the word 0, which the rANS pass reports as GMM_ERANGE. With clear,
+// the first workgroup also zeroes clear[0 .. nclear) (the call's status
+// words and the rANS pass's look-back slots, used only by the kernels
+// after this one), which saves a launch.
 template <int K, int kKind, bool kFast, bool kGather = false>
 __global__ void k_enc_cdf(fgmm::QCfg q, int64_t n, const int32_t* __restrict__ sym,
                           const float* __restrict__ w, const float* __restrict__ mu,
                           const float* __restrict__ sg, uint32_t* __restrict__ cf,
                           uint32_t* status, const int32_t* __restrict__ idx = nullptr,
-                          int64_t n_total = 0) {
+                          int64_t n_total = 0, uint32_t* clear = nullptr, int64_t nclear = 0) {
   using namespace fgmm;
   set_wave_priority(q.prio);
+  if (clear && blockIdx.x == 0)
+    for (int64_t k = threadIdx.x; k < nclear; k += blockDim.x) clear[k] = 0u;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (kGather)
-    cf[i] = enc_cdf_elem<K, kKind, kFast>(q, n_total, gather_index(idx, i, n_total), sym, w, mu,
-                                           sg, status);
+    cf[i] = enc_cdf_elem<K, kKind, kFast, true>(q, n_total, gather_index(idx, i, n_total), sym,
+                                                 w, mu, sg, status);
   else
-    cf[i] = enc_cdf_elem<K, kKind, kFast>(q, n, i, sym, w, mu, sg, status);
+    cf[i] = enc_cdf_elem<K, kKind, kFast, true>(q, n, i, sym, w, mu, sg, status);
 }
 
 // Decode with L lanes per stream (L = 1: one lane per stream and a binary

@@ -199,8 +199,10 @@ __device__ __forceinline__ int32_t search_group(const Elem<K>& e, const QCfg& q,
 }
 
 // Encode phase 1 for element i: (c_j << 16) | f_j of its symbol (both fit
-// 16 bits: c_j < M <= 2^16 for j < N, f_j <= M - N + 1 < 2^16).
-template <int K, int kKind, bool kFast>
+// 16 bits: c_j < M <= 2^16 for j < N, f_j <= M - N + 1 < 2^16). A symbol
+// outside [lo, hi] sets kStRange in *status, or with kSentinel gives the
+// word 0 (f = 0, which no valid symbol has), which the rANS pass reports.
+template <int K, int kKind, bool kFast, bool kSentinel = false>
 __device__ __forceinline__ uint32_t enc_cdf_elem(const QCfg& q, int64_t n, int64_t i,
                                                  const int32_t* __restrict__ sym,
                                                  const float* __restrict__ w,
@@ -209,14 +211,15 @@ __device__ __forceinline__ uint32_t enc_cdf_elem(const QCfg& q, int64_t n, int64
   float rw[K], rm[K], rs[K];
   load_raw<K>(w, mu, sg, n, i, rw, rm, rs);
   int32_t j = sym[i] - q.lo;
-  if (j < 0 || j >= q.N) {
-    atomicOr(status, kStRange);
+  const bool out = j < 0 || j >= q.N;
+  if (out) {
+    if (!kSentinel) atomicOr(status, kStRange);
     j = 0;
   }
   const Elem<K> e = make_elem<K, kFast, kKind>(q, rw, rm, rs);
   const uint32_t c0 = cdf_at<K, kKind, kFast>(e, q, j);
   const uint32_t c1 = cdf_at<K, kKind, kFast>(e, q, j + 1);
-  return (c0 << 16) | (c1 - c0);
+  return (kSentinel && out) ? 0u : ((c0 << 16) | (c1 - c0));
 }
 
 // s_waitcnt immediate: vector memory count 0, the other counters unlimited.
@@ -252,7 +255,8 @@ __device__ __forceinline__ void rans_put(uint32_t& x, uint32_t cfw, int P, int s
 // Encode phase 2 for stream s: the integer rANS recurrence over the packed
 // (c, f) words cf[s + p S], p = n_s-1 .. 0. The k-th emitted word goes to
 // region_end[-k], so the words end up in the order the decoder reads them.
-// Returns the final state; *count receives the number of words.
+// Returns the final state; *count receives the number of words, *zero_f
+// whether a word had f = 0 (an out-of-range symbol, see enc_cdf_elem).
 //
 // Memory operations are arranged so that every wait is for work issued a
 // whole block of kDepth steps earlier: the (c, f) words are loaded a block
@@ -261,7 +265,7 @@ __device__ __forceinline__ void rans_put(uint32_t& x, uint32_t cfw, int P, int s
 __device__ __forceinline__ uint32_t rans_stream(int64_t n, int64_t S, int P, int64_t s,
                                                 const uint32_t* __restrict__ cf,
                                                 uint16_t* __restrict__ region_end,
-                                                uint32_t* count) {
+                                                uint32_t* count, bool* zero_f) {
   const int64_t ns = stream_len(n, S, s);
   uint32_t x = 1u << 16;
   uint32_t cnt = 0;
@@ -278,6 +282,7 @@ __device__ __forceinline__ uint32_t rans_stream(int64_t n, int64_t S, int P, int
   const int64_t step = (int64_t)kDepth * S;
   uint32_t pend[kDepth];   // words emitted by the previous block (bit d of pmask: step d emitted)
   uint32_t pmask = 0, pbase = 0;
+  bool zf = false;
   for (int64_t p = ns - 1; p >= 0; p -= kDepth) {
     base -= step;  // position p - kDepth
     // everything issued so far is a block old: the loads of this block's
@@ -305,6 +310,7 @@ __device__ __forceinline__ uint32_t rans_stream(int64_t n, int64_t S, int P, int
     for (int d = 0; d < kDepth; ++d) {
       if (p - d < 0) break;
       bool emit;
+      zf = zf || (cur[d] & 0xFFFFu) == 0u;
       rans_put(x, cur[d], P, shift, emit, pend[d]);
       pmask |= (emit ? 1u : 0u) << d;
       cnt += emit ? 1u : 0u;
@@ -316,6 +322,7 @@ __device__ __forceinline__ uint32_t rans_stream(int64_t n, int64_t S, int P, int
       region_end[-(int64_t)(pbase + __builtin_popcount(pmask & ((1u << d) - 1u)))] =
           (uint16_t)pend[d];
   *count = cnt;
+  *zero_f = zf;
   return x;
 }
 
@@ -325,10 +332,12 @@ __device__ __forceinline__ uint32_t rans_stream(int64_t n, int64_t S, int P, int
 // (c, f) words are loaded a block of kDepth steps ahead as in rans_stream;
 // the LDS stores do not count on the vector-memory counter, so the one wait
 // per block is for those loads only. Returns the final state; *count
-// receives the number of words (at most n_s).
+// receives the number of words (at most n_s), *zero_f whether a word had
+// f = 0.
 __device__ __forceinline__ uint32_t rans_stream_lds(int64_t n, int64_t S, int P, int64_t s,
                                                     const uint32_t* __restrict__ cf,
-                                                    uint16_t* col, int stride, uint32_t* count) {
+                                                    uint16_t* col, int stride, uint32_t* count,
+                                                    bool* zero_f) {
   const int64_t ns = stream_len(n, S, s);
   uint32_t x = 1u << 16;
   uint32_t cnt = 0;
@@ -342,6 +351,7 @@ __device__ __forceinline__ uint32_t rans_stream_lds(int64_t n, int64_t S, int P,
 #pragma unroll
   for (int d = 0; d < kDepth; ++d) buf[d] = (ns - 1 - d >= 0) ? cf[base - dS[d]] : 0u;
   const int64_t step = (int64_t)kDepth * S;
+  bool zf = false;
   for (int64_t p = ns - 1; p >= 0; p -= kDepth) {
     base -= step;  // position p - kDepth
     __builtin_amdgcn_s_waitcnt(kWaitVm0);
@@ -359,12 +369,14 @@ __device__ __forceinline__ uint32_t rans_stream_lds(int64_t n, int64_t S, int P,
       if (p - d < 0) break;
       bool emit;
       uint32_t word;
+      zf = zf || (cur[d] & 0xFFFFu) == 0u;
       rans_put(x, cur[d], P, shift, emit, word);
       if (emit) col[cnt * stride] = (uint16_t)word;
       cnt += emit ? 1u : 0u;
     }
   }
   *count = cnt;
+  *zero_f = zf;
   return x;
 }
 
