@@ -109,35 +109,141 @@ class Latent:
         assert torch.equal(self.dec, self.lat.symbols), "round trip failed"
 
 
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(oracle, ocfg, sym, w, mu, sg, runs=3):
+    """Median over `runs` of the oracle's encode and decode wall times on one
+    latent (round trip checked); returns (enc_s, dec_s, bitstream)."""
+    import numpy as np
+    te, td = [], []
+    bs = None
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        st, bs, off = oracle.encode(ocfg, sym, w, mu, sg)
+        t1 = time.perf_counter()
+        st2, dec = oracle.decode(ocfg, bs, off, w, mu, sg)
+        t2 = time.perf_counter()
+        assert st == 0 and st2 == 0 and np.array_equal(dec, sym)
+        te.append(t1 - t0)
+        td.append(t2 - t1)
+    med = lambda v: sorted(v)[len(v) // 2]  # noqa: E731
+    return med(te), med(td), bs
+
+
+def _stream_sample(sym, w, mu, sg, S, streams):
+    """The first `streams` of the S streams of a latent as a latent of its
+    own (elements s + p S, s < streams, in the same stream layout)."""
+    import numpy as np
+    n = sym.size
+    idx = np.concatenate([np.arange(s, n, S) for s in range(streams)])
+    # element s + p S of stream s becomes element s + p streams
+    order = np.lexsort((idx % S, idx // S))
+    idx = idx[order]
+    return (np.ascontiguousarray(sym[idx]),) + tuple(np.ascontiguousarray(x[:, idx])
+                                                     for x in (w, mu, sg))
+
+
 def cpu_baseline(lat_host, cfgd):
     """The oracle (whole CDF column per element, table-lookup encode,
-    linear-scan decode) on the host cores, on a bounded sample: the whole
-    320x48x32 latent (about 30 s of CPU work)."""
-    import numpy as np
-
+    linear-scan decode) on the host: on all cores, the whole 320x48x32
+    latent, and on one core, its first 256 of 4,096 streams (a latent of
+    30,720 symbols in the same layout); each the median of 3 runs of encode
+    and of decode (about 15 s of CPU work in all)."""
     import oracle
     oracle.lib()
     sym, w, mu, sg, S = lat_host["sym"], lat_host["w"], lat_host["mu"], lat_host["sg"], lat_host["S"]
     ocfg = oracle.make_cfg(cfgd.K, cfgd.lo, cfgd.hi, cfgd.precision, S)
-    t0 = time.perf_counter()
-    st, bs, off = oracle.encode(ocfg, sym, w, mu, sg)
-    t1 = time.perf_counter()
-    st2, dec = oracle.decode(ocfg, bs, off, w, mu, sg)
-    t2 = time.perf_counter()
-    assert st == 0 and st2 == 0 and np.array_equal(dec, sym)
+    import numpy as np
+    cores = oracle.num_threads()
+    te, td, bs = _oracle_rate(oracle, ocfg, sym, w, mu, sg)
     m = sym.size
-    return {"value": m / (t2 - t0), "unit": "symbols/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"whole 320x48x32 latent, {S} streams ({m} symbols encoded and decoded); "
-                      f"encode {m / (t1 - t0):.4g} sym/s, decode {m / (t2 - t1):.4g} sym/s",
+    sub = _stream_sample(sym, w, mu, sg, S, 256)
+    oracle.set_num_threads(1)
+    try:
+        te1, td1, _ = _oracle_rate(oracle, oracle.make_cfg(cfgd.K, cfgd.lo, cfgd.hi,
+                                                           cfgd.precision, 256), *sub)
+    finally:
+        oracle.set_num_threads(cores)
+    m1 = sub[0].size
+    return {"value": m / (te + td), "unit": "symbols/s", "cores": cores, "kind": "oracle",
+            "sample": f"whole 320x48x32 latent, {S} streams ({m} symbols encoded and decoded), "
+                      "median of 3 runs",
+            "encode_sym_s": m / te, "decode_sym_s": m / td,
+            "one_core": {"value": m1 / (te1 + td1), "encode_sym_s": m1 / te1,
+                         "decode_sym_s": m1 / td1,
+                         "sample": "first 256 of the 4,096 streams of the 320x48x32 latent "
+                                   f"({m1} symbols), median of 3 runs"},
+            "cpu_model": _cpu_model(),
             "bitstream_equal_to_gpu": bool(np.array_equal(bs, lat_host.get("gpu_bs", bs)))}
 
 
-def summarize_prof(root: str) -> str:
-    """Markdown summary of rocprofv3 CSV output under root/{trace,fetch,write,
-    valu}: per (kernel, grid) mean duration, HBM bytes from FETCH_SIZE and
-    WRITE_SIZE scaled so that the 1 GiB calibration copy reads 1 GiB each
-    way, and VALU instruction counts."""
+def cpu_baseline_legs(dev) -> dict:
+    """Longer oracle legs (bench.py --cpu-baseline-legs, minutes of CPU
+    work): all cores, median of 3, on the whole 320x135x240 latent; on the
+    first 7 latents of the 64-latent batch (11.6% of its symbols) and on the
+    first 2 latents of the 256-latent K = 5 batch (1.5% of its symbols, one
+    run: the oracle's column of 1,023 entries per element makes 10% of it
+    hours of CPU work), each encoded and decoded."""
+    import numpy as np
+    import oracle
+    from paper_2509_18815_amd import synth
+    oracle.lib()
+    cores = oracle.num_threads()
+    out = {"cores": cores, "cpu_model": _cpu_model(), "kind": "oracle", "unit": "symbols/s"}
+    legs = [("c2b", None, 3), ("c3", 7, 3), ("c5", 2, 1)]
+    for name, limit, runs in legs:
+        cfgd = synth.CONFIGS[name]
+        lats = synth.make_latents(cfgd, backend="torch", device=dev, limit=limit)
+        total = sum(c * h * wd for c, h, wd in synth.batch_shapes(cfgd))
+        n_all, t_e, t_d = 0, 0.0, 0.0
+        for L in lats:
+            h = [x.cpu().numpy() for x in (L.symbols, L.weights, L.means, L.scales)]
+            ocfg = oracle.make_cfg(cfgd.K, cfgd.lo, cfgd.hi, cfgd.precision, L.streams)
+            te, td, _ = _oracle_rate(oracle, ocfg, *h, runs=runs)
+            n_all += L.n
+            t_e += te
+            t_d += td
+        out[name] = {"latents": len(lats), "symbols": n_all, "share_of_workload": n_all / total,
+                     "runs": runs, "value": n_all / (t_e + t_d), "encode_sym_s": n_all / t_e,
+                     "decode_sym_s": n_all / t_d}
+    return out
+
+
+def peak_probes(api, dev) -> dict:
+    """Measured ceilings of this GPU beside the published peaks: the issue
+    rate of independent binary32 fmas in this build's (non-packed) form, and
+    a 1 GiB device copy (bytes read + written per second)."""
+    import torch
+    stream = torch.cuda.current_stream()
+    lanes = 256 * 4 * 64 * 8          # 8 wavefronts per SIMD of 256 CUs
+    iters = 4096
+    out = torch.empty(lanes, dtype=torch.float32, device=dev)
+    t_fma = time_events(lambda: api.fma_probe(out, iters), 5, stream)
+    src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    t_cp = time_events(lambda: api.copy_probe(src, dst), 5, stream)
+    torch.cuda.synchronize()
+    assert bool(torch.equal(src[:1024], dst[:1024]))
+    del src, dst
+    fma_s = lanes * iters * 8 / t_fma
+    return {"fp32_fma_lane_per_s": float("%.4g" % fma_s),
+            "fp32_nonpacked_TFLOPs": round(2 * fma_s / 1e12, 2),
+            "hbm_copy_GBps": round(2 * (1 << 30) / t_cp / 1e9, 1)}
+
+
+def _prof_tables(root: str):
+    """Per (kernel, grid): kernel-trace durations (root/trace) and counter
+    means (root/fetch, root/write, root/valu: FETCH_SIZE, WRITE_SIZE,
+    SQ_INSTS_VALU, SQ_WAVES, ...), and the FETCH/WRITE scales that make the
+    largest runtime copy (the 1 GiB calibration copy) read 1 GiB each way."""
     import collections
     import csv
     import glob
@@ -149,7 +255,7 @@ def summarize_prof(root: str) -> str:
         return out
 
     def short(name):
-        name = name.replace("void ", "")
+        name = name.replace("void ", "").replace("(anonymous namespace)::", "")
         return name.split("(")[0] if "(" in name else name
 
     dur = collections.defaultdict(list)
@@ -162,7 +268,6 @@ def summarize_prof(root: str) -> str:
             ctr[(short(r["Kernel_Name"]), int(r["Grid_Size"]), r["Counter_Name"])].append(
                 float(r["Counter_Value"]))
     mean = lambda v: sum(v) / len(v) if v else float("nan")  # noqa: E731
-    # calibration: the largest copyBuffer dispatch is the 1 GiB copy
     cal = [k for k in ctr if k[0].startswith("__amd_rocclr_copyBuffer") and k[2] == "WRITE_SIZE"]
     gib_kib = float(1 << 20)
     fetch_f = write_f = float("nan")
@@ -172,26 +277,75 @@ def summarize_prof(root: str) -> str:
         kf = (kw[0], kw[1], "FETCH_SIZE")
         if kf in ctr:
             fetch_f = gib_kib / mean(ctr[kf])
-    lines = ["| kernel | grid | calls | mean us | median us | HBM read MB | HBM write MB | "
-             "VALU instr/wave | waves | GRBM_GUI_ACTIVE |",
-             "|---|---|---|---|---|---|---|---|---|---|"]
+    return dur, ctr, fetch_f, write_f, mean
+
+
+def kernel_records(root: str, prefixes=("k_", "kb_")) -> list:
+    """One record per (kernel, grid) of this library: calls, mean and median
+    duration, HBM bytes read and written per launch (scaled counters), VALU
+    wavefront instructions per launch, and the rates they give at the mean
+    duration: HBM GB/s against 8 TB/s and VALU lane-instructions per second
+    against the non-packed issue rate of 256 CU x 4 SIMD x 16 lanes x
+    2.4 GHz."""
+    dur, ctr, fetch_f, write_f, mean = _prof_tables(root)
     keys = sorted({(k[0], k[1]) for k in dur} | {(k[0], k[1]) for k in ctr},
                   key=lambda k: -mean(dur.get(k, [0])) * len(dur.get(k, [0])))
+    out = []
     for k in keys:
-        if not (k[0].startswith("k_") or k[0].startswith("__amd_rocclr_copyBuffer")):
+        if not k[0].startswith(prefixes):
             continue
         d = dur.get(k, [])
-        fe = mean(ctr.get((k[0], k[1], "FETCH_SIZE"), [])) * fetch_f * 1024 / 1e6
-        wr = mean(ctr.get((k[0], k[1], "WRITE_SIZE"), [])) * write_f * 1024 / 1e6
+        t = mean(d) * 1e-6
+        rd = mean(ctr.get((k[0], k[1], "FETCH_SIZE"), [])) * fetch_f * 1024
+        wr = mean(ctr.get((k[0], k[1], "WRITE_SIZE"), [])) * write_f * 1024
         vi = mean(ctr.get((k[0], k[1], "SQ_INSTS_VALU"), []))
         wv = mean(ctr.get((k[0], k[1], "SQ_WAVES"), []))
-        gg = mean(ctr.get((k[0], k[1], "GRBM_GUI_ACTIVE"), []))
-        med = sorted(d)[len(d) // 2] if d else float("nan")
-        lines.append(f"| {k[0]} | {k[1]} | {len(d)} | {mean(d):.2f} | {med:.2f} | {fe:.2f} | {wr:.2f} | "
-                     f"{vi / wv if wv == wv and wv else float('nan'):.0f} | {wv:.0f} | {gg:.0f} |")
+        rec = {"kernel": k[0], "grid": k[1], "calls": len(d), "mean_us": round(mean(d), 2),
+               "median_us": round(sorted(d)[len(d) // 2], 2) if d else None,
+               "read_MB": round(rd / 1e6, 3), "write_MB": round(wr / 1e6, 3),
+               "valu_wave_instructions": vi, "waves": wv}
+        if d and rd == rd:
+            rec["hbm_GBps"] = round((rd + wr) / t / 1e9, 1)
+            rec["hbm_frac"] = round((rd + wr) / t / 1e9 / PEAK_HBM_GBS, 4)
+        if d and vi == vi:
+            rec["valu_issue_frac"] = round(vi * 64 / t / VALU_ISSUE_PEAK, 4)
+        out.append(rec)
+    return out
+
+
+def summarize_prof(root: str) -> str:
+    """Markdown summary of rocprofv3 CSV output under root/{trace,fetch,write,
+    valu}: per (kernel, grid) mean duration, HBM bytes from FETCH_SIZE and
+    WRITE_SIZE scaled so that the 1 GiB calibration copy reads 1 GiB each
+    way, VALU instruction counts, and the HBM and VALU-issue fractions they
+    give at the mean duration."""
+    _, _, fetch_f, write_f, _ = _prof_tables(root)
+    lines = ["| kernel | grid | calls | mean us | median us | HBM read MB | HBM write MB | "
+             "VALU instr/wave | waves | HBM GB/s (frac of 8 TB/s) | VALU issue frac |",
+             "|---|---|---|---|---|---|---|---|---|---|---|"]
+    for r in kernel_records(root, ("k_", "kb_", "__amd_rocclr_copyBuffer")):
+        vw = (r["valu_wave_instructions"] / r["waves"]
+              if r["waves"] == r["waves"] and r["waves"] else float("nan"))
+        hb = f"{r['hbm_GBps']} ({r['hbm_frac']})" if "hbm_GBps" in r else "-"
+        lines.append(f"| {r['kernel']} | {r['grid']} | {r['calls']} | {r['mean_us']} | "
+                     f"{r['median_us']} | {r['read_MB']} | {r['write_MB']} | {vw:.0f} | "
+                     f"{r['waves']:.0f} | {hb} | {r.get('valu_issue_frac', '-')} |")
     head = [f"FETCH_SIZE scale {fetch_f:.4f}, WRITE_SIZE scale {write_f:.4f} "
             "(so that the 1 GiB calibration copy reads 1 GiB each way).", ""]
     return "\n".join(head + lines)
+
+
+def library_source_hash() -> str:
+    """sha256 of every HIP source of the library: per-kernel counter records
+    are reported only while the sources they were taken from are unchanged."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2509_18815_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*"))):
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 # the sources the dominant kernel (the single-latent decode) is compiled from
@@ -241,8 +395,28 @@ def traffic_record(root: str, kernel: str, grid: int) -> dict:
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_decode_4k_320x135x240_traffic.json")
+# per-kernel counter records of the batched and bracket forms (bench.py
+# --record-counters <profile dir>), tied to the library's source hash
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "kernel_counters.json")
+# the oracle's longer CPU legs, written by a run with --cpu-baseline-legs
+CPU_LEGS_FILE = os.path.join(ROOT, "profiles", "oracle_cpu_legs.json")
 # the dominant kernel: plain A&S decode, K=3, one lane per stream, direct indexing
 DOMINANT_KERNEL = "k_decode<3, 0, true, 1, false>"
+
+
+def form_counters(name: str):
+    """The committed counter records of a form's kernels (HBM and VALU-issue
+    fractions per kernel from a profiled run of that form), or None once the
+    library's sources have changed since they were taken."""
+    if not os.path.exists(COUNTERS_FILE):
+        return None
+    rec = json.load(open(COUNTERS_FILE)).get(name)
+    if not rec or rec.get("source_sha") != library_source_hash():
+        return None
+    keep = ("kernel", "grid", "calls", "mean_us", "read_MB", "write_MB", "hbm_GBps",
+            "hbm_frac", "valu_issue_frac")
+    return {"source": os.path.relpath(COUNTERS_FILE, ROOT),
+            "kernels": [{k: r[k] for k in keep if k in r} for r in rec["kernels"]]}
 
 
 def time_events(fn, reps, stream):
@@ -575,6 +749,15 @@ def main():
     if len(sys.argv) > 2 and sys.argv[1] == "--summarize-prof":
         print(summarize_prof(sys.argv[2]))
         return
+    if len(sys.argv) > 3 and sys.argv[1] == "--record-counters":
+        # bench.py --record-counters <profile dir> <form name>
+        allrec = json.load(open(COUNTERS_FILE)) if os.path.exists(COUNTERS_FILE) else {}
+        allrec[sys.argv[3]] = {"source_sha": library_source_hash(),
+                               "kernels": kernel_records(sys.argv[2])}
+        with open(COUNTERS_FILE, "w") as fh:
+            json.dump(allrec, fh, indent=1)
+        print(json.dumps(allrec[sys.argv[3]])[:2000])
+        return
     if len(sys.argv) > 2 and sys.argv[1] == "--record-traffic":
         rec = traffic_record(sys.argv[2], DOMINANT_KERNEL, 65536)
         with open(TRAFFIC_FILE, "w") as fh:
@@ -596,6 +779,15 @@ def main():
                     help="training tuples of each bracket model (c4, c5)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
+    ap.add_argument("--bracket-model", default=None,
+                    help="directory holding trained bracket models c1.npz, c4.npz, c5.npz "
+                         "(train.BracketModel.save format): loaded instead of trained")
+    ap.add_argument("--save-bracket-models", default=None,
+                    help="directory to save the bracket models trained in this run")
+    ap.add_argument("--cpu-baseline-legs", default=None,
+                    help="also time the oracle's longer legs (whole 4K latent, subsets of the "
+                         "batches; minutes of CPU work) and write them to this JSON file")
+    ap.add_argument("--no-peak-probes", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -746,32 +938,49 @@ def main():
         "roofline": roofline,
         "forms": forms,
     }
+    if not args.no_peak_probes:
+        roofline["peaks_measured"] = peak_probes(api, dev)
     want = [f for f in args.forms.split(",") if f and f != "none"]
     if "c3" in want:
         forms["c3_batched"] = batched_form(api, synth, "c3", dev)
+        forms["c3_batched"]["counters"] = form_counters("c3")
     if "c4" in want or "c5" in want:
         from paper_2509_18815_amd import train
+
+    def bracket_model(name, **kw):
+        """A trained bracket model: loaded from --bracket-model, else
+        trained here on the GPU (and saved with --save-bracket-models)."""
+        if args.bracket_model:
+            m = train.BracketModel.from_file(os.path.join(args.bracket_model, name + ".npz"))
+            m.history.append({"loaded_from": name + ".npz"})
+            return m
+        cfgd = synth.CONFIGS[name]
+        m = train.train_bracket(cfgd.K, cfgd.lo, cfgd.hi, cfgd.precision,
+                                n_train=args.bracket_tuples, device=dev, **kw)
+        if args.save_bracket_models:
+            os.makedirs(args.save_bracket_models, exist_ok=True)
+            m.save(os.path.join(args.save_bracket_models, name + ".npz"))
+        return m
     if "c4" in want:
-        c4 = synth.CONFIGS["c4"]
-        m4 = train.train_bracket(c4.K, c4.lo, c4.hi, c4.precision, n_train=args.bracket_tuples,
-                                 seed=synth.TRAIN_SEED_C4, device=dev)
+        m4 = bracket_model("c4", seed=synth.TRAIN_SEED_C4)
         forms["c4_bracket"] = bracket_single_form(api, synth, dev, m4)
+        forms["c4_bracket"]["counters"] = form_counters("c4")
         # the same model (same parameter distributions and support) on the
         # Kodak-size latent, whose 4,096 streams decode with 16 lanes each
         forms["c2a_bracket"] = bracket_few_streams_form(api, synth, dev, "c2a", m4)
         forms["step_learned_bracket"] = learned_step_form(api, lats, m4, step, args.steps,
                                                           args.warmup, value, dev)
-        c1 = synth.CONFIGS["c1"]
-        m1 = train.train_bracket(c1.K, c1.lo, c1.hi, c1.precision, n_train=args.bracket_tuples,
-                                 seed=synth.TRAIN_SEED_C1, device=dev)
+        m1 = bracket_model("c1", seed=synth.TRAIN_SEED_C1)
         forms["c1_bracket"] = bracket_few_streams_form(api, synth, dev, "c1", m1)
     if "c5" in want:
         c5 = synth.CONFIGS["c5"]
-        m5 = train.train_bracket(c5.K, c5.lo, c5.hi, c5.precision, n_train=args.bracket_tuples,
-                                 seed=synth.TRAIN_SEED_C5, s_logit=c5.s_logit, s_mu=c5.s_mu,
-                                 sigma_max=c5.sigma_max, device=dev)
+        # trained until the held-out hit rate stops improving (at most 24
+        # epochs of the 10 M tuples)
+        m5 = bracket_model("c5", seed=synth.TRAIN_SEED_C5, s_logit=c5.s_logit, s_mu=c5.s_mu,
+                           sigma_max=c5.sigma_max, epochs=24, plateau=5e-4)
         forms["c5_batched_bracket"] = batched_form(api, synth, "c5", dev, reps=3,
                                                    bracket_model=m5, loop_baseline=False)
+        forms["c5_batched_bracket"]["counters"] = form_counters("c5")
     if "table2" in want:
         forms["table2_cdf_kinds"] = table2_form(api, synth, dev)
     if "epilogue" in want:
@@ -790,6 +999,14 @@ def main():
                 "mu": L.lat.means.cpu().numpy(), "sg": L.lat.scales.cpu().numpy(), "S": L.S,
                 "gpu_bs": L.bs[: int(L.off[-1].item())].cpu().numpy().view(np.uint16)}
         out["cpu_baseline"] = cpu_baseline(host, L.cfgd)
+        if os.path.exists(CPU_LEGS_FILE):
+            out["cpu_baseline"]["legs"] = json.load(open(CPU_LEGS_FILE))
+            out["cpu_baseline"]["legs"]["source"] = os.path.relpath(CPU_LEGS_FILE, ROOT)
+    if args.cpu_baseline_legs:
+        legs = cpu_baseline_legs(dev)
+        with open(args.cpu_baseline_legs, "w") as fh:
+            json.dump(legs, fh, indent=1)
+        out.setdefault("cpu_baseline", {})["legs"] = legs
     print(json.dumps(out))
 
 

@@ -263,8 +263,8 @@ int gmm_decode(const gmm_cfg* cfg, int64_t n, const uint16_t* bitstream, int64_t
  * throughput form for serving many images at once. */
 typedef struct gmm_plan gmm_plan;
 
-/* Flag for gmm_plan_create: time every candidate launch shape (lanes per
- * stream, schedule, waves per compute unit) on the real shapes at the first
+/* Flag for gmm_plan_create: time every candidate launch shape
+ * (gmm_plan_config) on the real shapes at the first
  * gmm_plan_exec and keep the fastest; with the environment variable
  * FLASHGMM_TUNE_CACHE naming a file, results are cached there by shape
  * signature. Without it a fixed default shape is used. */
@@ -288,11 +288,31 @@ typedef struct gmm_latent_io {
   int32_t* decoded;
 } gmm_latent_io;
 
-/* Chosen launch shape of a plan (after its first execution). schedule:
- * 0 one work item per workgroup, 1 persistent with an atomic queue,
- * 2 persistent with a static round-robin assignment. */
+/* Launch shape of a plan (the autotuner's search space; the output never
+ * depends on it):
+ *  lanes_per_stream  decode: 1, 2, 4, 8 or 16 lanes share a stream and
+ *                    search (lanes+1)-ary; encode and bracket decode: 1
+ *  streams_per_lane  encode with lds_staging: 1, or 2 streams stepped in turn
+ *                    by one lane (two independent rANS chains per lane);
+ *                    otherwise 1
+ *  schedule          0 one work item per workgroup, 1 persistent workgroups
+ *                    with an atomic queue, 2 persistent with a static
+ *                    round-robin assignment
+ *  waves_per_cu      wavefronts per compute unit of the persistent grids,
+ *                    1..64
+ *  lds_staging       encode: 1 = each work item keeps its streams'
+ *                    renormalisation words in LDS and writes offsets and
+ *                    segments itself (per-latent decoupled look-back; streams
+ *                    of at most 300 symbols; schedules 0 and 1), 0 = words
+ *                    through scratch rows, then scan and pack kernels */
+typedef struct gmm_plan_config {
+  int32_t lanes_per_stream, streams_per_lane, schedule, waves_per_cu, lds_staging;
+} gmm_plan_config;
+
+/* State of a plan after its first execution: the chosen launch shape. */
 typedef struct gmm_plan_info_t {
-  int32_t tuned, lanes_per_stream, schedule, waves_per_cu, candidates, graph_captured;
+  int32_t tuned, candidates, graph_captured;
+  gmm_plan_config config;
   double best_ms;
 } gmm_plan_info_t;
 
@@ -320,15 +340,17 @@ int gmm_plan_info(const gmm_plan* plan, gmm_plan_info_t* info);
 int gmm_plan_set_bracket(gmm_plan* plan, const gmm_bracket* bracket, gmm_decode_stats* stats);
 
 /* Forces a launch shape (skipping the tuner) and drops the captured graph;
- * the next gmm_plan_exec captures again. lanes 1, 2, 4, 8 or 16 (decode
- * only; encode requires 1), schedule 0..2, waves_per_cu 1..64. For tests
- * and sweeps: the output never depends on it. */
-int gmm_plan_set_config(gmm_plan* plan, int32_t lanes, int32_t schedule, int32_t waves_per_cu);
+ * the next gmm_plan_exec captures again. GMM_EINVAL for a shape outside
+ * gmm_plan_config's ranges or not built for the plan (lds_staging with
+ * decode, schedule 2 or streams over 300 symbols; streams_per_lane 2
+ * without lds_staging). For tests and sweeps: the output never depends on
+ * it. */
+int gmm_plan_set_config(gmm_plan* plan, const gmm_plan_config* config);
 
-/* The tuner's candidate launch shapes: writes up to max_count triples
- * (lanes, schedule, waves_per_cu) to out [host, int32 3*max_count] and
- * returns the number of candidates (-1 on a NULL plan). */
-int gmm_plan_candidates(const gmm_plan* plan, int32_t* out, int32_t max_count);
+/* The tuner's candidate launch shapes: writes up to max_count of them to out
+ * [host, nullable] and returns the number of candidates (-1 on a NULL
+ * plan). */
+int gmm_plan_candidates(const gmm_plan* plan, gmm_plan_config* out, int32_t max_count);
 
 /* Releases a plan (waits for its work to finish). */
 int gmm_plan_destroy(gmm_plan* plan);
@@ -374,6 +396,16 @@ int gmm_fast_recip_mismatches(uint64_t* count, void* stream);
  * 1..8, n < 0 or NULL planes with n > 0. */
 int gmm_params_from_raw(int32_t K, int64_t n, const float* logits, const float* log_scales,
                         float* weights, float* scales, void* stream);
+
+/* ---- Peak probes (diagnostics; not part of the coder) ----
+ * gmm_fma_probe: `threads` lanes (a multiple of 256) each run 8 independent
+ * chains of `iters` binary32 fused multiply-adds (one fma per lane per
+ * instruction, as this build compiles them) and store a sum to out [device,
+ * float32 [threads]]; lane-fmas = threads * iters * 8. gmm_copy_probe:
+ * copies `bytes` (a multiple of 16) from src to dst [device]. Both are
+ * asynchronous on stream; the caller times them. GMM_EINVAL on bad sizes. */
+int gmm_fma_probe(float* out, int64_t threads, int32_t iters, void* stream);
+int gmm_copy_probe(const void* src, void* dst, int64_t bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -68,6 +68,7 @@ def lib():
             "gmm_oracle_decode": (ctypes.c_int, [cfgp, i64, P, i64, P, P, P, P, P]),
             "gmm_oracle_inverse": (ctypes.c_int, [cfgp, i64, P, P, P, P, P]),
             "gmm_oracle_num_threads": (i32, []),
+            "gmm_oracle_set_num_threads": (None, [i32]),
             "gmm_oracle_exp_d": (ctypes.c_double, [ctypes.c_double]),
             "gmm_oracle_tail_ref": (ctypes.c_double, [ctypes.c_double]),
             "gmm_oracle_phi_ref": (ctypes.c_double, [ctypes.c_double]),
@@ -225,6 +226,11 @@ def decode(cfg: Cfg, bitstream, offsets, w, mu, sig, n=None):
 
 def num_threads() -> int:
     return int(lib().gmm_oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's later parallel loops."""
+    lib().gmm_oracle_set_num_threads(int(n))
 
 
 def mlp_num_params(D: int, H: int = 64) -> int:

@@ -306,6 +306,14 @@ int32_t gmm_oracle_num_threads(void) {
 #endif
 }
 
+void gmm_oracle_set_num_threads(int32_t n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* ---------------- configuration checks ---------------- */
 static int check_cfg(const gmm_oracle_cfg* c, int64_t n) {
   if (!c || n < 0) return ORC_EINVAL;

@@ -88,6 +88,8 @@ int gmm_oracle_inverse(const gmm_oracle_cfg* cfg, int64_t n, const float* w,
                        int32_t* j_out);
 
 int32_t gmm_oracle_num_threads(void);
+/* Threads of the oracle's later parallel loops (OpenMP); n >= 1. */
+void gmm_oracle_set_num_threads(int32_t n);
 
 #ifdef __cplusplus
 }

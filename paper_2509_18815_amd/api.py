@@ -49,10 +49,19 @@ class LatentIO(ctypes.Structure):
                 ("offsets", ctypes.c_void_p), ("decoded", ctypes.c_void_p)]
 
 
-class PlanInfo(ctypes.Structure):
-    _fields_ = [("tuned", ctypes.c_int32), ("lanes_per_stream", ctypes.c_int32),
+class PlanConfig(ctypes.Structure):
+    _fields_ = [("lanes_per_stream", ctypes.c_int32), ("streams_per_lane", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
-                ("candidates", ctypes.c_int32), ("graph_captured", ctypes.c_int32),
+                ("lds_staging", ctypes.c_int32)]
+
+    def astuple(self):
+        return (self.lanes_per_stream, self.streams_per_lane, self.schedule, self.waves_per_cu,
+                self.lds_staging)
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("tuned", ctypes.c_int32), ("candidates", ctypes.c_int32),
+                ("graph_captured", ctypes.c_int32), ("config", PlanConfig),
                 ("best_ms", ctypes.c_double)]
 
 
@@ -80,7 +89,7 @@ _SIGS = {
     "gmm_plan_create": (ctypes.c_int, [_CFG, _I32, _P, _P, _I32, _I32, _P]),
     "gmm_plan_exec": (ctypes.c_int, [_P, _P, _P, _P]),
     "gmm_plan_info": (ctypes.c_int, [_P, _P]),
-    "gmm_plan_set_config": (ctypes.c_int, [_P, _I32, _I32, _I32]),
+    "gmm_plan_set_config": (ctypes.c_int, [_P, _P]),
     "gmm_plan_candidates": (ctypes.c_int, [_P, _P, _I32]),
     "gmm_plan_destroy": (ctypes.c_int, [_P]),
     "gmm_plan_set_bracket": (ctypes.c_int, [_P, _P, _P]),
@@ -91,6 +100,8 @@ _SIGS = {
     "gmm_bracket_create": (ctypes.c_int, [_P, _P]),
     "gmm_bracket_destroy": (ctypes.c_int, [_P]),
     "gmm_bracket_predict": (ctypes.c_int, [_P, _I32, _I64, _P, _P, _P, _P, _P, _P]),
+    "gmm_fma_probe": (ctypes.c_int, [_P, _I64, _I32, _P]),
+    "gmm_copy_probe": (ctypes.c_int, [_P, _P, _I64, _P]),
     "gmm_mlp_num_params": (ctypes.c_int, [_I32]),
     "gmm_mlp_workspace_bytes": (_I64, [_I32, _I64]),
     "gmm_mlp_features": (ctypes.c_int, [_I32, _I64, _P, _P, _P, _P, _I32, _P, _P, _I32, _P, _P]),
@@ -358,14 +369,18 @@ class Plan:
     def info(self) -> dict:
         inf = PlanInfo()
         _check(lib().gmm_plan_info(self.handle, ctypes.byref(inf)), "plan_info")
-        return {"tuned": bool(inf.tuned), "lanes_per_stream": inf.lanes_per_stream,
-                "schedule": SCHEDULES[inf.schedule], "waves_per_cu": inf.waves_per_cu,
+        c = inf.config
+        return {"tuned": bool(inf.tuned), "lanes_per_stream": c.lanes_per_stream,
+                "streams_per_lane": c.streams_per_lane, "schedule": SCHEDULES[c.schedule],
+                "waves_per_cu": c.waves_per_cu, "lds_staging": bool(c.lds_staging),
                 "candidates": inf.candidates, "graph_captured": bool(inf.graph_captured),
                 "best_ms": inf.best_ms}
 
-    def set_config(self, lanes, schedule, waves_per_cu):
-        _check(lib().gmm_plan_set_config(self.handle, lanes, schedule, waves_per_cu),
-               "plan_set_config")
+    def set_config(self, lanes, streams_per_lane, schedule, waves_per_cu, lds_staging):
+        """Forces a launch shape; the arguments are a candidate tuple."""
+        c = PlanConfig(int(lanes), int(streams_per_lane), int(schedule), int(waves_per_cu),
+                       int(lds_staging))
+        _check(lib().gmm_plan_set_config(self.handle, ctypes.byref(c)), "plan_set_config")
 
     def set_bracket(self, bracket, stats=None):
         """Decode plans: use the learned bracket (None = plain search)."""
@@ -375,10 +390,12 @@ class Plan:
         self._bracket = bracket
 
     def candidates(self):
+        """The tuner's launch shapes as tuples (lanes_per_stream,
+        streams_per_lane, schedule, waves_per_cu, lds_staging)."""
         n = lib().gmm_plan_candidates(self.handle, None, 0)
-        buf = (ctypes.c_int32 * (3 * max(n, 1)))()
+        buf = (PlanConfig * max(n, 1))()
         lib().gmm_plan_candidates(self.handle, buf, n)
-        return [tuple(buf[3 * i: 3 * i + 3]) for i in range(n)]
+        return [buf[i].astuple() for i in range(n)]
 
     def close(self):
         if self.handle:
@@ -488,6 +505,22 @@ def mlp_adam(params, grad, m, v, lr, step, grad_scale, shadow=None, beta1=0.9, b
                               _dev(v, torch.float32, "v"), float(lr), float(beta1),
                               float(beta2), float(eps), int(step), float(grad_scale),
                               _opt(shadow, torch.float32, "shadow"), _stream()), "mlp_adam")
+
+
+def fma_probe(out, iters, stream=None):
+    """Launches the FP32 fma issue probe over out.numel() lanes (see
+    gmm_fma_probe); lane-fmas = out.numel() * iters * 8."""
+    _check(lib().gmm_fma_probe(_dev(out, torch.float32, "out"), out.numel(), int(iters),
+                               _stream(stream)), "fma_probe")
+
+
+def copy_probe(src, dst, stream=None):
+    """Launches the device copy probe of src into dst (same byte size)."""
+    if src.numel() * src.element_size() != dst.numel() * dst.element_size():
+        raise ValueError("src and dst differ in size")
+    _check(lib().gmm_copy_probe(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                src.numel() * src.element_size(), _stream(stream)),
+           "copy_probe")
 
 
 def checkerboard_indices(C, H, W, anchor=True, device="cuda"):

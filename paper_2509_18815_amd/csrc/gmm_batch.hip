@@ -6,15 +6,19 @@
 // streams start on a block boundary, so a block always belongs to one
 // latent (found through a block -> latent table):
 //   encode: kb_enc_cdf (one thread per element of every latent)
-//           kb_enc_rans (256 streams per work item; persistent workgroups
-//                        pull items from an atomic queue, longest streams
-//                        first, or take them statically or one per block)
-//           kb_scan (one workgroup per latent)  kb_pack  kb_finalize
+//           kb_enc_rans_lds (256 streams per work item, words in LDS, one
+//                        pass with a per-latent look-back; persistent
+//                        workgroups pull items from an atomic queue, longest
+//                        streams first, or one item per workgroup)  kb_finalize
+//           or kb_enc_rans (words through scratch rows; queue, static or one
+//                        item per block)  kb_scan (one workgroup per latent)
+//           kb_pack  kb_finalize
 //   decode: kb_decode (one wavefront per work item of 64/L streams, L lanes
 //                      per stream; persistent/dynamic, persistent/static or
 //                      one item per block)          kb_finalize
-// The launch shape (lanes per stream, schedule, waves per compute unit) is
-// chosen by timing every candidate on the real shapes at the first
+// The launch shape (lanes per stream, streams per lane, schedule, waves per
+// compute unit, LDS staging of the encoder's words) is chosen by timing
+// every candidate on the real shapes at the first
 // execution (the output is identical for every candidate), optionally
 // cached in a file keyed by the shape signature, and the chosen sequence is
 // captured once into a hipGraph that later executions launch.
@@ -159,6 +163,97 @@ __global__ void __launch_bounds__(kPBlock)
                l, kPLanes);
 }
 
+// rANS pass with the renormalisation words staged in LDS, one pass per work
+// item (a rANS block: 256 streams of one latent), in place of kb_enc_rans,
+// kb_scan and kb_pack. SPL streams per lane: 1 (256 threads) or 2 (128
+// threads, each stepping streams t and t + 128 in turn: two independent
+// chains per lane). Items are taken from the queue in its order, which
+// keeps each latent's items in stream order, so the item's offset in its
+// latent comes from a decoupled look-back over the latent's earlier items
+// (slots of the latent, zeroed before the launch); every item waited on has
+// been taken by a running workgroup. The item writes its streams' offsets
+// and, when its range fits the latent's capacity, their segments straight
+// into the latent's bitstream; the item with the latent's last streams
+// writes offsets[S] and flags ENOSPC. Dynamic LDS: words[cap][256] for the
+// largest cap of the plan. Schedules: flat (one item per workgroup, taken
+// by ticket) and dynamic.
+template <int SPL>
+__global__ void __launch_bounds__(kRBlock / SPL)
+    kb_enc_rans_lds(const LatentDesc* __restrict__ desc, int P, const int32_t* __restrict__ items,
+                    int64_t n_items, int sched, uint32_t* queue,
+                    const int32_t* __restrict__ blk_latent, const uint32_t* __restrict__ cf,
+                    uint64_t* slots, uint32_t* status) {
+  extern __shared__ uint16_t words[];  // [cap][kRBlock]
+  __shared__ int64_t item_sh, excl_sh;
+  __shared__ uint32_t tot_a_sh;
+  constexpr int T = kRBlock / SPL;
+  for (;;) {
+    if (threadIdx.x == 0) item_sh = (int64_t)atomicAdd(queue, 1u);
+    __syncthreads();
+    const int64_t item = item_sh;
+    if (item >= n_items) break;
+    const int64_t blk = items[item];
+    const int b = blk_latent[blk];
+    const LatentDesc& d = desc[b];
+    const int64_t k = blk - d.rans_blk0;  // item index within its latent
+    const uint32_t* lcf = cf + d.elem_base;
+    const int64_t sa = k * kRBlock + threadIdx.x, sb = sa + T;
+    uint32_t xa = 1u << 16, xb = 1u << 16, ca = 0, cb = 0;
+    bool zf = false;
+    if (SPL == 1) {
+      if (sa < d.S) xa = rans_stream_lds(d.n, d.S, P, sa, lcf, words + threadIdx.x, kRBlock, &ca,
+                                         &zf);
+    } else if (sa < d.S) {
+      // a lane whose second stream lies past S steps its first one twice;
+      // the copy's words go to an unused column and are dropped
+      rans_stream_lds2(d.n, d.S, P, sa, sb < d.S ? sb : sa, lcf, words + threadIdx.x,
+                       words + threadIdx.x + T, kRBlock, xa, xb, ca, cb, zf);
+      if (sb >= d.S) cb = 0;
+    }
+    (void)zf;  // plans report ranges in phase 1 (no f = 0 words)
+    uint32_t tot, la, lb = 0;
+    la = block_excl_scan<T>((sa < d.S) ? ca + 2u : 0u, &tot);
+    if (SPL == 2) {
+      if (threadIdx.x == 0) tot_a_sh = tot;
+      __syncthreads();
+      uint32_t tot_b;
+      lb = tot_a_sh + block_excl_scan<T>((sb < d.S) ? cb + 2u : 0u, &tot_b);
+      tot += tot_b;
+    }
+    if (threadIdx.x < 64) {
+      const int64_t e = lookback_prefix(slots + d.rans_blk0, k, (int64_t)tot);
+      if (threadIdx.x == 0) excl_sh = e;
+    }
+    __syncthreads();
+    const int64_t excl = excl_sh;
+    if (sa < d.S) d.offsets[sa] = excl + (int64_t)la;
+    if (SPL == 2 && sb < d.S) d.offsets[sb] = excl + (int64_t)lb;
+    if (k == d.nblk - 1 && threadIdx.x == 0) {
+      const int64_t total = excl + (int64_t)tot;
+      d.offsets[d.S] = total;
+      if (total > d.words) atomicOr(&status[b], kStNoSpace);
+    }
+    if (excl + (int64_t)tot <= d.words) {
+      // each lane writes its own streams' segments: the state words, then the
+      // renormalisation words in decoder order (newest first)
+#pragma unroll
+      for (int j = 0; j < SPL; ++j) {
+        const int64_t s = j ? sb : sa;
+        if (s < d.S) {
+          const uint32_t x = j ? xb : xa, cnt = j ? cb : ca;
+          const int64_t o = excl + (int64_t)(j ? lb : la);
+          d.bs[o] = (uint16_t)(x & 0xFFFFu);
+          d.bs[o + 1] = (uint16_t)(x >> 16);
+          const uint16_t* col = words + threadIdx.x + j * T;
+          for (uint32_t t = 0; t < cnt; ++t) d.bs[o + 2 + t] = col[(cnt - 1u - t) * kRBlock];
+        }
+      }
+    }
+    if (sched == kFlat) break;
+    __syncthreads();  // LDS words, the scans' LDS and item_sh are reused next item
+  }
+}
+
 // Work item = (latent, first stream) of 64/L streams; one wavefront each.
 template <int K, int kKind, bool kFast, int L>
 __global__ void __launch_bounds__(64)
@@ -241,8 +336,12 @@ __global__ void kb_finalize(const uint32_t* __restrict__ bits, int32_t B,
 }
 
 struct Config {
-  int32_t lanes = 1, sched = kDynamic, waves_per_cu = 8;
+  int32_t lanes = 1, spl = 1, sched = kDynamic, waves_per_cu = 8, lds = 0;
 };
+
+// Largest dynamic LDS of kb_enc_rans_lds (words of a work item's 256
+// streams): streams of up to 300 symbols.
+constexpr int64_t kRansLdsMax = 300 * kRBlock * 2;
 
 bool same_io(const gmm_latent_io& a, const gmm_latent_io& b) {
   return memcmp(&a, &b, sizeof(gmm_latent_io)) == 0;
@@ -286,7 +385,10 @@ struct gmm_plan {
   const gmm_bracket* bracket = nullptr;
   unsigned long long* stats = nullptr;
   // status
-  uint32_t* d_bits = nullptr;  // [B] status bits, then the queue counter
+  uint32_t* d_bits = nullptr;  // [B] status bits, the queue counter, look-back slots
+  uint64_t* d_slots = nullptr; // [n_rans_blk] look-back slots (inside d_bits)
+  int64_t reset_words = 0;     // words of d_bits cleared before each execution
+  int64_t cap_max = 1;         // longest stream of the plan (LDS words per stream)
   int32_t* d_codes = nullptr;  // [B]
   // chosen configuration and graph
   Config conf;
@@ -348,8 +450,8 @@ int build_decode_items(gmm_plan* p, int L, hipStream_t st) {
 // Enqueues one execution of the plan with configuration c on stream st.
 int enqueue(gmm_plan* p, const Config& c, hipStream_t st) {
   const int B = p->B;
-  hipLaunchKernelGGL(kb_reset, dim3((unsigned)((B + 1 + 255) / 256)), dim3(256), 0, st, p->d_bits,
-                     (int64_t)(B + 1));
+  hipLaunchKernelGGL(kb_reset, dim3((unsigned)((p->reset_words + 255) / 256)), dim3(256), 0, st,
+                     p->d_bits, p->reset_words);
   uint32_t* queue = p->d_bits + B;
   const int64_t persist_grid = (int64_t)p->num_cus * c.waves_per_cu;
   if (p->op == 0) {
@@ -360,6 +462,26 @@ int enqueue(gmm_plan* p, const Config& c, hipStream_t st) {
                            dim3((unsigned)p->n_cdf_blk), dim3(kCdfBlock), 0, st, p->d_desc, p->q,
                            p->d_cdf_blk, p->d_cf, p->d_bits);
       });
+    }
+    if (c.lds) {
+      // one pass per item, words in LDS; workgroups of 256 / spl threads
+      const int wpb = (kRBlock / c.spl) / 64;
+      const int64_t grid =
+          (c.sched == kFlat) ? p->n_rans_blk
+                             : std::min<int64_t>(p->n_rans_blk,
+                                                 std::max<int64_t>(1, persist_grid / wpb));
+      const size_t lds = (size_t)(p->cap_max * kRBlock * 2);
+      if (c.spl == 2)
+        hipLaunchKernelGGL(kb_enc_rans_lds<2>, dim3((unsigned)grid), dim3(kRBlock / 2), lds, st,
+                           p->d_desc, p->cfg.precision, p->d_rans_items, p->n_rans_blk, c.sched,
+                           queue, p->d_rans_blk, p->d_cf, p->d_slots, p->d_bits);
+      else
+        hipLaunchKernelGGL(kb_enc_rans_lds<1>, dim3((unsigned)grid), dim3(kRBlock), lds, st,
+                           p->d_desc, p->cfg.precision, p->d_rans_items, p->n_rans_blk, c.sched,
+                           queue, p->d_rans_blk, p->d_cf, p->d_slots, p->d_bits);
+      hipLaunchKernelGGL(kb_finalize, dim3((unsigned)((B + 63) / 64)), dim3(64), 0, st,
+                         p->d_bits, B, p->d_codes);
+      return hipGetLastError() == hipSuccess ? GMM_OK : GMM_EDEVICE;
     }
     // persistent grids of 4-wave workgroups: waves_per_cu / 4 per compute unit
     int64_t grid = (c.sched == kFlat) ? p->n_rans_blk
@@ -415,14 +537,35 @@ int enqueue(gmm_plan* p, const Config& c, hipStream_t st) {
   return hipGetLastError() == hipSuccess ? GMM_OK : GMM_EDEVICE;
 }
 
+// Lets kb_enc_rans_lds use more than the default dynamic LDS (once).
+bool lds_ready() {
+  static const bool ok =
+      hipFuncSetAttribute((const void*)kb_enc_rans_lds<1>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)kRansLdsMax) == hipSuccess &&
+      hipFuncSetAttribute((const void*)kb_enc_rans_lds<2>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)kRansLdsMax) == hipSuccess;
+  return ok;
+}
+
 std::vector<Config> candidates(const gmm_plan* p) {
   std::vector<Config> v;
   const int wpcs[] = {4, 8, 16};
   if (p->op == 0) {
-    v.push_back({1, kFlat, 8});
+    v.push_back({1, 1, kFlat, 8, 0});
     for (int w : wpcs) {
-      v.push_back({1, kDynamic, w});
-      v.push_back({1, kStatic, w});
+      v.push_back({1, 1, kDynamic, w, 0});
+      v.push_back({1, 1, kStatic, w, 0});
+    }
+    // words staged in LDS, one pass per item (flat by ticket or dynamic;
+    // a static assignment could wait on an item not yet started), one or
+    // two streams per lane
+    if (p->cap_max * kRBlock * 2 <= kRansLdsMax && lds_ready()) {
+      for (int spl : {1, 2}) {
+        v.push_back({1, spl, kFlat, 8, 1});
+        for (int w : wpcs) v.push_back({1, spl, kDynamic, w, 1});
+      }
     }
   } else {
     int64_t streams = 0;
@@ -430,10 +573,10 @@ std::vector<Config> candidates(const gmm_plan* p) {
     for (int L : {1, 2, 4, 8, 16}) {
       if (p->bracket && L != 1) continue;  // the bracket kernel runs one lane per stream
       if (L > 1 && streams * L > (int64_t)p->num_cus * 64 * 64) continue;  // > 16 waves / SIMD
-      v.push_back({L, kFlat, 8});
+      v.push_back({L, 1, kFlat, 8, 0});
       for (int w : wpcs) {
-        v.push_back({L, kDynamic, w});
-        v.push_back({L, kStatic, w});
+        v.push_back({L, 1, kDynamic, w, 0});
+        v.push_back({L, 1, kStatic, w, 0});
       }
     }
   }
@@ -453,7 +596,8 @@ std::string shape_signature(const gmm_plan* p) {
   return buf;
 }
 
-// Tuning cache: one line per signature, "<sig> <lanes> <sched> <waves_per_cu> <ms>".
+// Tuning cache: one line per signature,
+// "<sig> <lanes> <streams_per_lane> <sched> <waves_per_cu> <lds> <ms>".
 bool cache_lookup(const std::string& sig, Config* c, double* ms) {
   const char* path = getenv("FLASHGMM_TUNE_CACHE");
   if (!path || !*path) return false;
@@ -461,14 +605,16 @@ bool cache_lookup(const std::string& sig, Config* c, double* ms) {
   FILE* f = fopen(path, "r");
   if (!f) return false;
   char s[64];
-  int L, sc, w;
+  int L, spl, sc, w, lds;
   double t;
   bool found = false;
-  while (fscanf(f, "%63s %d %d %d %lf", s, &L, &sc, &w, &t) == 5) {
+  while (fscanf(f, "%63s %d %d %d %d %d %lf", s, &L, &spl, &sc, &w, &lds, &t) == 7) {
     if (sig == s) {
       c->lanes = L;
+      c->spl = spl;
       c->sched = sc;
       c->waves_per_cu = w;
+      c->lds = lds;
       *ms = t;
       found = true;
     }
@@ -483,12 +629,16 @@ void cache_store(const std::string& sig, const Config& c, double ms) {
   std::lock_guard<std::mutex> lk(g_cache_mu);
   FILE* f = fopen(path, "a");
   if (!f) return;
-  fprintf(f, "%s %d %d %d %.6f\n", sig.c_str(), c.lanes, c.sched, c.waves_per_cu, ms);
+  fprintf(f, "%s %d %d %d %d %d %.6f\n", sig.c_str(), c.lanes, c.spl, c.sched, c.waves_per_cu,
+          c.lds, ms);
   fclose(f);
 }
 
 Config default_config(const gmm_plan* p) {
   Config c;
+  // encode: words staged in LDS where the streams fit (measured 2-4% faster
+  // than the scratch rows on the 64- and 256-latent batches)
+  if (p->op == 0 && p->cap_max * kRBlock * 2 <= kRansLdsMax && lds_ready()) c.lds = 1;
   if (p->op == 1 && !p->bracket) {
     int64_t streams = 0;
     for (int b = 0; b < p->B; ++b) streams += p->S[b];
@@ -626,13 +776,19 @@ int gmm_plan_create(const gmm_cfg* common, int32_t B, const int64_t* n_b, const 
     for (int64_t k = 0; k < (d.S + per - 1) / per; ++k) pack_blk.push_back(b);
     d.scratch_base = scratch;
     scratch += d.S * d.cap;
+    p->cap_max = std::max<int64_t>(p->cap_max, d.cap);
   }
   p->n_cdf_blk = (int64_t)cdf_blk.size();
   p->n_rans_blk = (int64_t)rans_blk.size();
   p->n_pack_blk = (int64_t)pack_blk.size();
   int r = GMM_OK;
   r = r ? r : dev_alloc(p, &p->d_desc, B);
-  r = r ? r : dev_alloc(p, &p->d_bits, B + 1);
+  // status bits [B], the queue counter, then (encode) the look-back slots
+  // of the LDS-staged rANS pass at an 8-byte aligned offset
+  const int64_t slot_off = (B + 2) & ~(int64_t)1;
+  p->reset_words = (op == 0) ? slot_off + 2 * p->n_rans_blk : B + 1;
+  r = r ? r : dev_alloc(p, &p->d_bits, p->reset_words);
+  if (!r && op == 0) p->d_slots = (uint64_t*)(p->d_bits + slot_off);
   r = r ? r : dev_alloc(p, &p->d_codes, B);
   if (!r && hipHostMalloc((void**)&p->pinned_desc, sizeof(LatentDesc) * B, 0) != hipSuccess)
     r = GMM_ENOMEM;
@@ -745,21 +901,31 @@ int gmm_plan_exec(gmm_plan* p, const gmm_latent_io* io, int32_t* dev_status, voi
 int gmm_plan_info(const gmm_plan* p, gmm_plan_info_t* info) {
   if (!p || !info) return GMM_EINVAL;
   info->tuned = p->tuned ? 1 : 0;
-  info->lanes_per_stream = p->conf.lanes;
-  info->schedule = p->conf.sched;
-  info->waves_per_cu = p->conf.waves_per_cu;
   info->candidates = p->candidates;
-  info->best_ms = p->best_ms;
   info->graph_captured = p->gexec ? 1 : 0;
+  info->config.lanes_per_stream = p->conf.lanes;
+  info->config.streams_per_lane = p->conf.spl;
+  info->config.schedule = p->conf.sched;
+  info->config.waves_per_cu = p->conf.waves_per_cu;
+  info->config.lds_staging = p->conf.lds;
+  info->best_ms = p->best_ms;
   return GMM_OK;
 }
 
-int gmm_plan_set_config(gmm_plan* p, int32_t lanes, int32_t schedule, int32_t waves_per_cu) {
-  if (!p) return GMM_EINVAL;
+int gmm_plan_set_config(gmm_plan* p, const gmm_plan_config* config) {
+  if (!p || !config) return GMM_EINVAL;
+  const int32_t lanes = config->lanes_per_stream, spl = config->streams_per_lane;
+  const int32_t schedule = config->schedule, waves_per_cu = config->waves_per_cu;
+  const int32_t lds = config->lds_staging;
   if (lanes != 1 && lanes != 2 && lanes != 4 && lanes != 8 && lanes != 16) return GMM_EINVAL;
   if ((p->op == 0 || p->bracket) && lanes != 1) return GMM_EINVAL;
   if (schedule < kFlat || schedule > kStatic || waves_per_cu < 1 || waves_per_cu > 64)
     return GMM_EINVAL;
+  if (lds != 0 && lds != 1) return GMM_EINVAL;
+  if (lds && (p->op != 0 || schedule == kStatic || p->cap_max * kRBlock * 2 > kRansLdsMax ||
+              !lds_ready()))
+    return GMM_EINVAL;
+  if (spl != 1 && !(spl == 2 && lds)) return GMM_EINVAL;
   if (p->cap_stream) (void)hipStreamSynchronize(p->cap_stream);
   (void)hipDeviceSynchronize();
   if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
@@ -767,8 +933,10 @@ int gmm_plan_set_config(gmm_plan* p, int32_t lanes, int32_t schedule, int32_t wa
   p->gexec = nullptr;
   p->graph = nullptr;
   p->conf.lanes = lanes;
+  p->conf.spl = spl;
   p->conf.sched = schedule;
   p->conf.waves_per_cu = waves_per_cu;
+  p->conf.lds = lds;
   p->best_ms = -1.0;
   if (p->op == 1) {
     int r = build_decode_items(p, lanes, p->cap_stream);
@@ -796,14 +964,11 @@ int gmm_plan_set_bracket(gmm_plan* p, const gmm_bracket* bracket, gmm_decode_sta
   return GMM_OK;
 }
 
-int gmm_plan_candidates(const gmm_plan* p, int32_t* out, int32_t max_count) {
+int gmm_plan_candidates(const gmm_plan* p, gmm_plan_config* out, int32_t max_count) {
   if (!p) return -1;
   const std::vector<Config> v = candidates(p);
-  for (int32_t i = 0; i < (int32_t)v.size() && out && i < max_count; ++i) {
-    out[3 * i] = v[i].lanes;
-    out[3 * i + 1] = v[i].sched;
-    out[3 * i + 2] = v[i].waves_per_cu;
-  }
+  for (int32_t i = 0; i < (int32_t)v.size() && out && i < max_count; ++i)
+    out[i] = {v[i].lanes, v[i].spl, v[i].sched, v[i].waves_per_cu, v[i].lds};
   return (int32_t)v.size();
 }
 

@@ -380,6 +380,73 @@ __device__ __forceinline__ uint32_t rans_stream_lds(int64_t n, int64_t S, int P,
   return x;
 }
 
+// rans_stream_lds for two streams a and b of one latent in one lane, stepped
+// in turn at the same positions (their lengths differ by at most one), so
+// that the lane carries two independent dependency chains; the (c, f) words
+// of both are loaded a block ahead.
+__device__ __forceinline__ void rans_stream_lds2(int64_t n, int64_t S, int P, int64_t sa,
+                                                 int64_t sb, const uint32_t* __restrict__ cf,
+                                                 uint16_t* cola, uint16_t* colb, int stride,
+                                                 uint32_t& xa, uint32_t& xb, uint32_t& ca,
+                                                 uint32_t& cb, bool& zero_f) {
+  const int64_t na = stream_len(n, S, sa), nb = stream_len(n, S, sb);
+  const int64_t nmax = na > nb ? na : nb;
+  xa = xb = 1u << 16;
+  ca = cb = 0;
+  const int shift = 32 - P;
+  constexpr int kDepth = 8;
+  int64_t dS[kDepth];
+#pragma unroll
+  for (int d = 0; d < kDepth; ++d) dS[d] = (int64_t)d * S;
+  // positions past a stream's end (or below 0) reload its first element
+  auto at = [&](int64_t s, int64_t ns, int64_t pos) -> int64_t {
+    return (pos >= 0 && pos < ns) ? s + pos * S : s;
+  };
+  uint32_t bufa[kDepth], bufb[kDepth];
+#pragma unroll
+  for (int d = 0; d < kDepth; ++d) {
+    bufa[d] = cf[at(sa, na, nmax - 1 - d)];
+    bufb[d] = cf[at(sb, nb, nmax - 1 - d)];
+  }
+  bool zf = false;
+  for (int64_t p = nmax - 1; p >= 0; p -= kDepth) {
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
+    uint32_t cura[kDepth], curb[kDepth];
+#pragma unroll
+    for (int d = 0; d < kDepth; ++d) {
+      cura[d] = bufa[d];
+      curb[d] = bufb[d];
+    }
+#pragma unroll
+    for (int d = 0; d < kDepth; ++d) {
+      bufa[d] = cf[at(sa, na, p - kDepth - d)];
+      bufb[d] = cf[at(sb, nb, p - kDepth - d)];
+    }
+#pragma unroll
+    for (int d = 0; d < kDepth; ++d) {
+      const int64_t q = p - d;
+      if (q < 0) break;
+      if (q < na) {
+        bool emit;
+        uint32_t word;
+        zf = zf || (cura[d] & 0xFFFFu) == 0u;
+        rans_put(xa, cura[d], P, shift, emit, word);
+        if (emit) cola[ca * stride] = (uint16_t)word;
+        ca += emit ? 1u : 0u;
+      }
+      if (q < nb) {
+        bool emit;
+        uint32_t word;
+        zf = zf || (curb[d] & 0xFFFFu) == 0u;
+        rans_put(xb, curb[d], P, shift, emit, word);
+        if (emit) colb[cb * stride] = (uint16_t)word;
+        cb += emit ? 1u : 0u;
+      }
+    }
+  }
+  zero_f = zf;
+}
+
 // Sum of v over the 64 lanes of a wavefront (every lane receives it).
 __device__ __forceinline__ int64_t wave_sum64(int64_t v) {
 #pragma unroll

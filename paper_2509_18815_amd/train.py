@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import dataclasses
+import json
 import math
 import time
 
@@ -46,16 +47,20 @@ class BracketModel:
                            self.out_std, self.radius)
 
     def save(self, path: str) -> None:
+        """Plain arrays and a JSON string of the training history (loadable
+        without pickling)."""
         np.savez(path, K=self.K, lo=self.lo, hi=self.hi, precision=self.precision,
                  params=self.params, in_mean=self.in_mean, in_std=self.in_std,
-                 out_mean=self.out_mean, out_std=self.out_std, radius=self.radius)
+                 out_mean=self.out_mean, out_std=self.out_std, radius=self.radius,
+                 history=np.array(json.dumps(self.history)))
 
     @staticmethod
     def from_file(path: str) -> "BracketModel":
-        z = np.load(path)
+        z = np.load(path, allow_pickle=False)
+        hist = json.loads(str(z["history"])) if "history" in z.files else []
         return BracketModel(int(z["K"]), int(z["lo"]), int(z["hi"]), int(z["precision"]),
                             z["params"], z["in_mean"], z["in_std"], float(z["out_mean"]),
-                            float(z["out_std"]), int(z["radius"]))
+                            float(z["out_std"]), int(z["radius"]), hist)
 
 
 def make_tuples(K, lo, hi, precision, n, gen, device, s_logit=1.0, s_mu=2.0, sigma_max=20.0):
@@ -89,7 +94,11 @@ def init_params(D, seed):
 
 def train_bracket(K, lo, hi, precision=16, n_train=10_000_000, n_eval=262_144, epochs=6,
                   batch=8192, lr=3e-3, seed=6, s_logit=1.0, s_mu=2.0, sigma_max=20.0,
-                  radius=4, device="cuda", log=None) -> BracketModel:
+                  radius=4, device="cuda", log=None, plateau=None) -> BracketModel:
+    """Trains the bracket network. With plateau, training stops before
+    `epochs` once the held-out hit rate has gained less than plateau in each
+    of two consecutive epochs (the learning rate follows a cosine over
+    `epochs` either way)."""
     dev = torch.device(device)
     gen = torch.Generator(device=dev)
     gen.manual_seed(seed)
@@ -143,6 +152,10 @@ def train_bracket(K, lo, hi, precision=16, n_train=10_000_000, n_eval=262_144, e
         history.append(rec)
         if log:
             log(rec)
+        if (plateau is not None and len(history) >= 3
+                and history[-1]["hit_rate"] - history[-2]["hit_rate"] < plateau
+                and history[-2]["hit_rate"] - history[-3]["hit_rate"] < plateau):
+            break
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     model = BracketModel(K, lo, hi, precision, master.cpu().numpy(), mean.cpu().numpy(),
@@ -161,10 +174,11 @@ def main():
     ap.add_argument("--tuples", type=int, default=10_000_000)
     ap.add_argument("--epochs", type=int, default=6)
     ap.add_argument("--seed", type=int, default=synth.TRAIN_SEED_C4)
+    ap.add_argument("--plateau", type=float, default=None)
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
     model = train_bracket(a.K, a.lo, a.hi, a.precision, n_train=a.tuples, epochs=a.epochs,
-                          seed=a.seed, log=print)
+                          seed=a.seed, log=print, plateau=a.plateau)
     model.save(a.out)
     print(model.history[-1])
 
