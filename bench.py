@@ -119,21 +119,26 @@ def _cpu_model() -> str:
     return "unknown"
 
 
-def _oracle_rate(oracle, ocfg, sym, w, mu, sg, runs=3):
+def _oracle_rate(oracle, ocfg, sym, w, mu, sg, runs=3, progress=None):
     """Median over `runs` of the oracle's encode and decode wall times on one
-    latent (round trip checked); returns (enc_s, dec_s, bitstream)."""
+    latent (round trip checked); returns (enc_s, dec_s, bitstream). With
+    progress, a line per run goes to stderr (long legs)."""
     import numpy as np
     te, td = [], []
     bs = None
-    for _ in range(runs):
+    for r in range(runs):
         t0 = time.perf_counter()
         st, bs, off = oracle.encode(ocfg, sym, w, mu, sg)
         t1 = time.perf_counter()
+        if progress:
+            print(f"{progress}: run {r} encode {t1 - t0:.1f} s", file=sys.stderr, flush=True)
         st2, dec = oracle.decode(ocfg, bs, off, w, mu, sg)
         t2 = time.perf_counter()
         assert st == 0 and st2 == 0 and np.array_equal(dec, sym)
         te.append(t1 - t0)
         td.append(t2 - t1)
+        if progress:
+            print(f"{progress}: run {r} decode {t2 - t1:.1f} s", file=sys.stderr, flush=True)
     med = lambda v: sorted(v)[len(v) // 2]  # noqa: E731
     return med(te), med(td), bs
 
@@ -207,7 +212,8 @@ def cpu_baseline_legs(dev) -> dict:
         for L in lats:
             h = [x.cpu().numpy() for x in (L.symbols, L.weights, L.means, L.scales)]
             ocfg = oracle.make_cfg(cfgd.K, cfgd.lo, cfgd.hi, cfgd.precision, L.streams)
-            te, td, _ = _oracle_rate(oracle, ocfg, *h, runs=runs)
+            te, td, _ = _oracle_rate(oracle, ocfg, *h, runs=runs,
+                                     progress=f"oracle leg {name}, latent of {L.n} symbols")
             n_all += L.n
             t_e += te
             t_d += td
@@ -402,6 +408,11 @@ COUNTERS_FILE = os.path.join(ROOT, "profiles", "kernel_counters.json")
 CPU_LEGS_FILE = os.path.join(ROOT, "profiles", "oracle_cpu_legs.json")
 # the dominant kernel: plain A&S decode, K=3, one lane per stream, direct indexing
 DOMINANT_KERNEL = "k_decode<3, 0, true, 1, false>"
+
+
+def progress(msg: str) -> None:
+    """A progress line on stderr (long runs, profilers)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
 def form_counters(name: str):
@@ -846,6 +857,7 @@ def main():
     for _ in range(args.warmup):
         step()
 
+    progress(f"{args.warmup} warm-up steps done; timing {args.steps} steps")
     # timed region: K steps, bracketed by device synchronisation
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -942,6 +954,7 @@ def main():
         roofline["peaks_measured"] = peak_probes(api, dev)
     want = [f for f in args.forms.split(",") if f and f != "none"]
     if "c3" in want:
+        progress("form c3 (batch of 64 latents)")
         forms["c3_batched"] = batched_form(api, synth, "c3", dev)
         forms["c3_batched"]["counters"] = form_counters("c3")
     if "c4" in want or "c5" in want:
@@ -962,6 +975,7 @@ def main():
             m.save(os.path.join(args.save_bracket_models, name + ".npz"))
         return m
     if "c4" in want:
+        progress("form c4 (learned bracket, 4K latent; Kodak and 192x16x16 latents)")
         m4 = bracket_model("c4", seed=synth.TRAIN_SEED_C4)
         forms["c4_bracket"] = bracket_single_form(api, synth, dev, m4)
         forms["c4_bracket"]["counters"] = form_counters("c4")
@@ -973,6 +987,7 @@ def main():
         m1 = bracket_model("c1", seed=synth.TRAIN_SEED_C1)
         forms["c1_bracket"] = bracket_few_streams_form(api, synth, dev, "c1", m1)
     if "c5" in want:
+        progress("form c5 (batch of 256 K=5 latents, plain and learned bracket)")
         c5 = synth.CONFIGS["c5"]
         # trained until the held-out hit rate stops improving (at most 24
         # epochs of the 10 M tuples)
@@ -982,8 +997,10 @@ def main():
                                                    bracket_model=m5, loop_baseline=False)
         forms["c5_batched_bracket"]["counters"] = form_counters("c5")
     if "table2" in want:
+        progress("form table2 (Gaussian-CDF kinds)")
         forms["table2_cdf_kinds"] = table2_form(api, synth, dev)
     if "epilogue" in want:
+        progress("form epilogue (raw network outputs)")
         forms["raw_output_mapping"] = epilogue_form(api, synth, dev)
     if args.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB
