@@ -108,7 +108,10 @@ int gmm_cdf_table(const gmm_cfg* cfg, int64_t n, const float* weights, const flo
 int gmm_inverse_cdf(const gmm_cfg* cfg, int64_t n, const float* weights, const float* means,
                     const float* scales, const uint32_t* slot, int32_t* j_out, void* stream);
 
-/* Encode n symbols [device, int32] with parameter planes [device] into
+/* Encode (Sec. III-A: each element's quantized mixture CDF evaluated at the
+ * coded symbol's two boundaries, then the rANS state map of Eq. (3) per
+ * stream, last element first). Encode n symbols [device, int32] with
+ * parameter planes [device] into
  * bitstream [device, uint16, capacity_words] and offsets [device, int64,
  * S+1]: segment s occupies words offsets[s] .. offsets[s+1]-1 and
  * offsets[S] is the encoded size. GMM_ERANGE if a symbol is outside
@@ -239,7 +242,10 @@ int gmm_mlp_adam(int32_t P, float* params, const float* grad, float* m, float* v
                  float beta1, float beta2, float eps, int32_t step, float grad_scale,
                  float* shadow, void* stream);
 
-/* Decode n symbols [device, int32 out] from bitstream [device, uint16,
+/* Decode (Sec. III-A: per symbol a binary search for the slot over the
+ * monotone quantized CDF evaluated on the fly, then the inverse of the
+ * state map of Eq. (3)). Decode n symbols [device, int32 out] from
+ * bitstream [device, uint16,
  * total_words] and offsets [device, int64, S+1] with the same parameter
  * planes and configuration used to encode. GMM_ECORRUPT if a segment lies
  * outside the bitstream, is shorter than two words, is read past its end
