@@ -298,9 +298,10 @@ typedef struct gmm_latent_io {
  * depends on it):
  *  lanes_per_stream  decode: 1, 2, 4, 8 or 16 lanes share a stream and
  *                    search (lanes+1)-ary; encode and bracket decode: 1
- *  streams_per_lane  encode with lds_staging: 1, or 2 streams stepped in turn
- *                    by one lane (two independent rANS chains per lane);
- *                    otherwise 1
+ *  streams_per_lane  1, or 2 streams coded by one lane in lock-step (two
+ *                    independent rANS chains per lane, half the wavefronts):
+ *                    encode with lds_staging, and plain decode with one
+ *                    lane per stream; otherwise 1
  *  schedule          0 one work item per workgroup, 1 persistent workgroups
  *                    with an atomic queue, 2 persistent with a static
  *                    round-robin assignment
@@ -348,9 +349,9 @@ int gmm_plan_set_bracket(gmm_plan* plan, const gmm_bracket* bracket, gmm_decode_
 /* Forces a launch shape (skipping the tuner) and drops the captured graph;
  * the next gmm_plan_exec captures again. GMM_EINVAL for a shape outside
  * gmm_plan_config's ranges or not built for the plan (lds_staging with
- * decode, schedule 2 or streams over 300 symbols; streams_per_lane 2
- * without lds_staging). For tests and sweeps: the output never depends on
- * it. */
+ * decode, schedule 2 or streams over 300 symbols; streams_per_lane 2 for
+ * an encode without lds_staging, a bracket decode or lanes_per_stream > 1).
+ * For tests and sweeps: the output never depends on it. */
 int gmm_plan_set_config(gmm_plan* plan, const gmm_plan_config* config);
 
 /* The tuner's candidate launch shapes: writes up to max_count of them to out

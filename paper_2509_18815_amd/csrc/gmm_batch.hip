@@ -287,6 +287,39 @@ __global__ void __launch_bounds__(64)
   }
 }
 
+// Two streams per lane: work item = (latent, first stream) of 128 streams;
+// lane l decodes streams first + l and first + 64 + l together.
+template <int K, int kKind, bool kFast>
+__global__ void __launch_bounds__(64)
+    kb_decode2(const LatentDesc* __restrict__ desc, QCfg q, int P, int rounds,
+               const int2* __restrict__ items, int64_t n_items, int sched, uint32_t* queue,
+               uint32_t* status) {
+  const int lane = threadIdx.x;
+  int64_t it = blockIdx.x;
+  for (;;) {
+    int64_t item;
+    if (sched == kDynamic) {
+      uint32_t v = 0;
+      if (lane == 0) v = atomicAdd(queue, 1u);
+      item = (int64_t)__shfl(v, 0, 64);
+    } else {
+      item = it;
+    }
+    if (item >= n_items) break;
+    const int2 t = items[item];
+    const LatentDesc& d = desc[t.x];
+    const int64_t sa = (int64_t)t.y + lane;
+    if (sa < d.S) {
+      const bool bad = decode_stream2<K, kKind, kFast>(q, P, rounds, d.n, d.S, sa, sa + 64, d.bs,
+                                                       d.words, d.offsets, d.w, d.mu, d.sg,
+                                                       d.dec);
+      if (bad) atomicOr(&status[t.x], kStCorrupt);
+    }
+    if (sched == kFlat) break;
+    if (sched == kStatic) it += gridDim.x;
+  }
+}
+
 // Decode with the learned bracket: work item = (latent, first stream) of 64
 // streams, one wavefront each (the matrix-core inference needs all lanes).
 template <int K, int kKind, bool kFast>
@@ -377,10 +410,10 @@ struct gmm_plan {
   uint32_t *d_cf = nullptr, *d_xfin = nullptr, *d_count = nullptr, *d_local = nullptr;
   uint16_t* d_scratch = nullptr;
   int64_t *d_blk_total = nullptr, *d_blk_pre = nullptr;
-  // decode items (for the chosen lanes per stream)
+  // decode items (for the chosen lanes and streams per lane)
   int2* d_items = nullptr;
   int64_t n_items = 0;
-  int32_t items_lanes = 0;
+  int32_t items_per = 0;  // streams per item of the current list (0: none built)
   // learned bracket for decode (nullable) and its counters
   const gmm_bracket* bracket = nullptr;
   unsigned long long* stats = nullptr;
@@ -415,9 +448,12 @@ int dev_alloc(gmm_plan* p, T** out, int64_t count) {
   return GMM_OK;
 }
 
-int build_decode_items(gmm_plan* p, int L, hipStream_t st) {
-  if (p->items_lanes == L) return GMM_OK;
-  const int per = 64 / L;
+// Streams per decode work item: one wavefront's 64 lanes, L lanes per
+// stream, spl streams per lane.
+int item_streams(const Config& c) { return 64 / c.lanes * c.spl; }
+
+int build_decode_items(gmm_plan* p, int per, hipStream_t st) {
+  if (p->items_per == per) return GMM_OK;
   struct It {
     int2 v;
     int64_t cost;
@@ -443,7 +479,7 @@ int build_decode_items(gmm_plan* p, int L, hipStream_t st) {
     return GMM_EDEVICE;
   if (hipStreamSynchronize(st) != hipSuccess) return GMM_EDEVICE;
   p->n_items = (int64_t)h.size();
-  p->items_lanes = L;
+  p->items_per = per;
   return GMM_OK;
 }
 
@@ -507,6 +543,18 @@ int enqueue(gmm_plan* p, const Config& c, hipStream_t st) {
                              p->cfg.precision, p->d_items, p->n_items, c.sched, queue, p->d_bits,
                              p->bracket->dev, p->stats);
         }
+      });
+    }
+  } else if (c.spl == 2) {
+    const int rounds = search_rounds(p->q.N);
+    const int64_t grid = (c.sched == kFlat) ? p->n_items : std::min(p->n_items, persist_grid);
+    if (grid > 0) {
+      dispatch(p->cfg.K, p->cfg.cdf_kind, p->fast, [&](auto Kc, auto kc, auto fc) {
+        hipLaunchKernelGGL((kb_decode2<decltype(Kc)::value, decltype(kc)::value,
+                                       decltype(fc)::value>),
+                           dim3((unsigned)grid), dim3(64), 0, st, p->d_desc, p->q,
+                           p->cfg.precision, rounds, p->d_items, p->n_items, c.sched, queue,
+                           p->d_bits);
       });
     }
   } else {
@@ -577,6 +625,14 @@ std::vector<Config> candidates(const gmm_plan* p) {
       for (int w : wpcs) {
         v.push_back({L, 1, kDynamic, w, 0});
         v.push_back({L, 1, kStatic, w, 0});
+      }
+    }
+    // two streams per lane (one lane per stream, plain decode)
+    if (!p->bracket) {
+      v.push_back({1, 2, kFlat, 8, 0});
+      for (int w : wpcs) {
+        v.push_back({1, 2, kDynamic, w, 0});
+        v.push_back({1, 2, kStatic, w, 0});
       }
     }
   }
@@ -650,7 +706,7 @@ Config default_config(const gmm_plan* p) {
 
 int time_config(gmm_plan* p, const Config& c, hipStream_t st, double* ms) {
   int r = GMM_OK;
-  if (p->op == 1) r = build_decode_items(p, c.lanes, st);
+  if (p->op == 1) r = build_decode_items(p, item_streams(c), st);
   if (r) return r;
   hipEvent_t a, b;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return GMM_EDEVICE;
@@ -697,7 +753,7 @@ int tune(gmm_plan* p, hipStream_t st) {
   p->conf = c;
   p->best_ms = ms;
   if (p->op == 1) {
-    int r = build_decode_items(p, c.lanes, st);
+    int r = build_decode_items(p, item_streams(c), st);
     if (r) return r;
   }
   p->tuned = true;
@@ -925,7 +981,10 @@ int gmm_plan_set_config(gmm_plan* p, const gmm_plan_config* config) {
   if (lds && (p->op != 0 || schedule == kStatic || p->cap_max * kRBlock * 2 > kRansLdsMax ||
               !lds_ready()))
     return GMM_EINVAL;
-  if (spl != 1 && !(spl == 2 && lds)) return GMM_EINVAL;
+  // two streams per lane: the LDS-staged encode pass, or the plain decode
+  // with one lane per stream
+  if (spl != 1 && !(spl == 2 && (p->op == 0 ? lds == 1 : (!p->bracket && lanes == 1))))
+    return GMM_EINVAL;
   if (p->cap_stream) (void)hipStreamSynchronize(p->cap_stream);
   (void)hipDeviceSynchronize();
   if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
@@ -939,7 +998,7 @@ int gmm_plan_set_config(gmm_plan* p, const gmm_plan_config* config) {
   p->conf.lds = lds;
   p->best_ms = -1.0;
   if (p->op == 1) {
-    int r = build_decode_items(p, lanes, p->cap_stream);
+    int r = build_decode_items(p, item_streams(p->conf), p->cap_stream);
     if (r) return r;
   }
   p->tuned = true;
@@ -959,7 +1018,7 @@ int gmm_plan_set_bracket(gmm_plan* p, const gmm_bracket* bracket, gmm_decode_sta
   p->bracket = bracket;
   p->stats = (unsigned long long*)stats;
   p->tuned = false;
-  p->items_lanes = 0;
+  p->items_per = 0;
   p->signature = shape_signature(p);
   return GMM_OK;
 }

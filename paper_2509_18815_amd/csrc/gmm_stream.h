@@ -729,4 +729,147 @@ __device__ __forceinline__ bool decode_stream(const QCfg& q, int P, int rounds, 
   return bad || x != (1u << 16) || ptr != b;
 }
 
+// The looped binary search of search_bs for two elements at once: both run
+// the same rounds, so each round holds two independent CDF evaluations.
+template <int K, int kKind, bool kFast>
+__device__ __forceinline__ void search_bs2(const Elem<K>& ea, const Elem<K>& eb, const QCfg& q,
+                                           int rounds, int nfree, uint32_t sla, uint32_t slb,
+                                           int32_t& ja, uint32_t& cla, uint32_t& cha,
+                                           int32_t& jb, uint32_t& clb, uint32_t& chb) {
+  int32_t la = 0, lb = 0;
+  cla = 0;
+  clb = 0;
+  cha = q.M;
+  chb = q.M;
+  int r = rounds - 1;
+  for (int i = 0; i < nfree; ++i, --r) {
+    const int32_t ma = la + (1 << r), mb = lb + (1 << r);
+    const uint32_t ca = cdf_inner<K, kKind, kFast>(ea, q, ma);
+    const uint32_t cb = cdf_inner<K, kKind, kFast>(eb, q, mb);
+    const bool ra = sla >= ca, rb = slb >= cb;
+    la = ra ? ma : la;
+    cla = ra ? ca : cla;
+    cha = ra ? cha : ca;
+    lb = rb ? mb : lb;
+    clb = rb ? cb : clb;
+    chb = rb ? chb : cb;
+  }
+  for (; r >= 0; --r) {
+    const int32_t ma = la + (1 << r), mb = lb + (1 << r);
+    const uint32_t ca = cdf_upper<K, kKind, kFast>(ea, q, ma);
+    const uint32_t cb = cdf_upper<K, kKind, kFast>(eb, q, mb);
+    const bool ra = sla >= ca, rb = slb >= cb;
+    la = ra ? ma : la;
+    cla = ra ? ca : cla;
+    cha = ra ? cha : ca;
+    lb = rb ? mb : lb;
+    clb = rb ? cb : clb;
+    chb = rb ? chb : cb;
+  }
+  ja = la;
+  jb = lb;
+}
+
+// Decode of two streams sa < sb of one latent by one lane (two streams per
+// lane): the streams' steps run in lock-step in one loop and a step's two
+// searches share their rounds, so every step holds two independent
+// dependency chains, with half the wavefronts of one stream per lane. The
+// software pipeline is decode_stream's with a ring of two steps per stream.
+// sb >= S leaves the lane one stream: the second chain then repeats sa's
+// loads and never writes. sb's stream is never longer than sa's. A lane
+// whose offsets fail the checks decodes its streams one at a time with
+// decode_stream, which writes and reports them. Returns true if either
+// stream fails the integrity checks.
+template <int K, int kKind, bool kFast>
+__device__ __forceinline__ bool decode_stream2(const QCfg& q, int P, int rounds, int64_t n,
+                                               int64_t S, int64_t sa, int64_t sb,
+                                               const uint16_t* __restrict__ bs,
+                                               int64_t total_words,
+                                               const int64_t* __restrict__ offsets,
+                                               const float* __restrict__ w,
+                                               const float* __restrict__ mu,
+                                               const float* __restrict__ sg,
+                                               int32_t* __restrict__ sym) {
+  const bool two = sb < S;
+  const int64_t a0 = offsets[sa], a1 = offsets[sa + 1];
+  const int64_t b0 = two ? offsets[sb] : a0, b1 = two ? offsets[sb + 1] : a1;
+  if (a0 < 0 || a1 < a0 + 2 || a1 > total_words || b0 < 0 || b1 < b0 + 2 || b1 > total_words) {
+    bool bad = false;
+    for (int j = 0; j < (two ? 2 : 1); ++j)
+      bad = decode_stream<K, kKind, kFast, 1>(q, P, rounds, n, S, j ? sb : sa, 0, bs,
+                                              total_words, offsets, w, mu, sg, sym) ||
+            bad;
+    return bad;
+  }
+  const int64_t na = stream_len(n, S, sa), nb = two ? stream_len(n, S, sb) : 0;
+  uint32_t xa = (uint32_t)bs[a0] | ((uint32_t)bs[a0 + 1] << 16);
+  uint32_t xb = (uint32_t)bs[b0] | ((uint32_t)bs[b0 + 1] << 16);
+  int64_t pa = a0 + 2, pb = b0 + 2;
+  uint32_t wa = (pa < a1) ? bs[pa] : 0u, wb = (pb < b1) ? bs[pb] : 0u;
+  bool bad = xa < (1u << 16) || (two && xb < (1u << 16));
+  const uint32_t mask = q.M - 1;
+  if (na > 0) {
+    const int nfree = free_rounds(rounds, q.N);
+    constexpr int kRing = 2;
+    // element of position p of each stream, clamped to its last element (an
+    // empty second stream follows the first, so every load stays in the latent)
+    auto elem_a = [&](int64_t p) -> int64_t { return sa + (p < na - 1 ? p : na - 1) * S; };
+    auto elem_b = [&](int64_t p) -> int64_t {
+      return nb > 0 ? sb + (p < nb - 1 ? p : nb - 1) * S : elem_a(p);
+    };
+    float aw[kRing][K] = {}, am[kRing][K] = {}, as[kRing][K] = {};
+    float bw[kRing][K] = {}, bm[kRing][K] = {}, bsg[kRing][K] = {};
+    int64_t ga[kRing] = {}, gb[kRing] = {};
+    for (int64_t p0 = -kRing; p0 < na; p0 += kRing) {
+#pragma unroll
+      for (int d = 0; d < kRing; ++d) {
+        const int64_t p = p0 + d;
+        const bool liva = p >= 0 && p < na, livb = p >= 0 && p < nb;
+        const uint32_t sla = xa & mask, slb = xb & mask;
+        uint32_t cla = 0, cha = q.M, clb = 0, chb = q.M;
+        if (liva) {
+          float cw[K], cm[K], cs[K], dw[K], dm[K], ds[K];
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            cw[k] = opaque_copy(aw[d][k]);
+            cm[k] = opaque_copy(am[d][k]);
+            cs[k] = opaque_copy(as[d][k]);
+            dw[k] = opaque_copy(bw[d][k]);
+            dm[k] = opaque_copy(bm[d][k]);
+            ds[k] = opaque_copy(bsg[d][k]);
+          }
+          const Elem<K> ea = make_elem<K, kFast, kKind>(q, cw, cm, cs);
+          const Elem<K> eb = make_elem<K, kFast, kKind>(q, dw, dm, ds);
+          int32_t ja, jb;
+          search_bs2<K, kKind, kFast>(ea, eb, q, rounds, nfree, sla, slb, ja, cla, cha, jb, clb,
+                                      chb);
+          sym[ga[d]] = q.lo + ja;
+          if (livb) sym[gb[d]] = q.lo + jb;
+        }
+        const uint32_t xsa = (cha - cla) * (xa >> P) + sla - cla;
+        const uint32_t xsb = (chb - clb) * (xb >> P) + slb - clb;
+        const bool ra = liva && xsa < (1u << 16), rb = livb && xsb < (1u << 16);
+        const bool ha = pa < a1, hb = pb < b1;
+        const uint32_t xra = ra ? ((xsa << 16) | (ha ? wa : 0u)) : xsa;
+        const uint32_t xrb = rb ? ((xsb << 16) | (hb ? wb : 0u)) : xsb;
+        xa = liva ? xra : xa;
+        xb = livb ? xrb : xb;
+        bad = bad || (ra && !ha) || (rb && !hb);
+        pa += (ra && ha) ? 1 : 0;
+        pb += (rb && hb) ? 1 : 0;
+        wa = bs[pa < a1 ? pa : a1 - 1];
+        wb = bs[pb < b1 ? pb : b1 - 1];
+        asm volatile("" ::: "memory");  // keep the words' loads ahead of the rings'
+        ga[d] = elem_a(p + kRing);
+        gb[d] = elem_b(p + kRing);
+        load_raw<K>(w, mu, sg, n, ga[d], aw[d], am[d], as[d]);
+        load_raw<K>(w, mu, sg, n, gb[d], bw[d], bm[d], bsg[d]);
+      }
+    }
+  }
+  bad = bad || xa != (1u << 16) || pa != a1;
+  if (two) bad = bad || xb != (1u << 16) || pb != b1;
+  return bad;
+}
+
 }  // namespace fgmm

@@ -172,6 +172,80 @@ def test_plan_status_per_latent(api):
     pd.close()
 
 
+def test_two_streams_per_lane_decode_corruption(api):
+    """Decode with two streams per lane (every such candidate): clean
+    latents decode exactly; a flipped word marks its latent corrupt and
+    leaves every other stream exact; broken offsets send the lane to the
+    one-stream path, which writes the smallest symbol for the broken streams
+    and decodes the lane's other stream exactly. Latent 1 has 64 streams
+    (lanes with one stream), latents 2 and 5 pair streams s and s + 64."""
+    lats = make_batch(5, SHAPES[2:8])
+    ns, Ss = [L["n"] for L in lats], [L["S"] for L in lats]
+    pe = api.Plan(K, LO, HI, P, ns, Ss, op=0, autotune=False)
+    io = enc_io(lats)
+    assert pe.run(io) == api.OK
+    pd = api.Plan(K, LO, HI, P, ns, Ss, op=1, autotune=False)
+    cands = [c for c in pd.candidates() if c[1] == 2]
+    assert cands, "no two-streams-per-lane decode candidate"
+
+    def stream_elems(b, s):
+        return np.arange(s, lats[b]["n"], lats[b]["S"])
+
+    for cand in cands:
+        pd.set_config(*cand)
+        assert pd.info()["streams_per_lane"] == 2
+        # clean
+        dio = dec_io(lats, io)
+        status = torch.full((len(lats),), -7, dtype=torch.int32, device="cuda")
+        assert pd.run(dio, status=status) == api.OK, cand
+        torch.cuda.synchronize()
+        assert status.cpu().tolist() == [0] * len(lats), cand
+        check_dec(dio, lats)
+        # a flipped renormalisation word in latent 1 stream 1 and latent 5 stream 70
+        dio = dec_io(lats, io)
+        saved = []
+        for b, s in ((1, 1), (5, 70)):
+            bsw = dio[b]["bitstream"]
+            pos = int(dio[b]["offsets"][s].item()) + 2
+            saved.append((bsw, pos, bsw[pos].item()))
+            bsw[pos] ^= 0x0101
+        status = torch.zeros(len(lats), dtype=torch.int32, device="cuda")
+        assert pd.run(dio, status=status) == api.OK, cand
+        torch.cuda.synchronize()
+        st = status.cpu().tolist()
+        assert st[1] == api.ECORRUPT and st[5] == api.ECORRUPT, (cand, st)
+        assert all(v == 0 for i, v in enumerate(st) if i not in (1, 5)), (cand, st)
+        for b, d in enumerate(dio):
+            got = d["decoded"].cpu().numpy()
+            keep = np.ones(lats[b]["n"], dtype=bool)
+            for bb, s in ((1, 1), (5, 70)):
+                if bb == b:
+                    keep[stream_elems(b, s)] = False
+            assert np.array_equal(got[keep], lats[b]["sym"][keep]), (cand, b)
+        for bsw, pos, v in saved:
+            bsw[pos] = v
+        # broken offsets in latent 2: streams 2 and 3 (paired with 66 and 67)
+        dio = dec_io(lats, io)
+        bad_off = dio[2]["offsets"].clone()
+        bad_off[3] = -5
+        dio[2]["offsets"] = bad_off
+        status = torch.zeros(len(lats), dtype=torch.int32, device="cuda")
+        assert pd.run(dio, status=status) == api.OK, cand
+        torch.cuda.synchronize()
+        st = status.cpu().tolist()
+        assert st[2] == api.ECORRUPT and all(v == 0 for i, v in enumerate(st) if i != 2), st
+        got = dio[2]["decoded"].cpu().numpy()
+        broken = np.concatenate([stream_elems(2, 2), stream_elems(2, 3)])
+        assert np.all(got[broken] == LO), cand
+        keep = np.ones(lats[2]["n"], dtype=bool)
+        keep[broken] = False
+        assert np.array_equal(got[keep], lats[2]["sym"][keep]), cand
+        for b in (0, 1, 3, 4, 5):
+            assert np.array_equal(dio[b]["decoded"].cpu().numpy(), lats[b]["sym"]), (cand, b)
+    pe.close()
+    pd.close()
+
+
 def test_batch_of_64_uneven_latents(api, orc):
     """The 64-latent batch (192 x H x W, H, W ~ U{8..128}), autotuned: round
     trip of every latent, three latents equal to the single-latent calls,
