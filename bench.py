@@ -587,9 +587,10 @@ def bracket_single_form(api, synth, dev, model, reps=5):
 
 def bracket_few_streams_form(api, synth, dev, name, model, reps=10):
     """A latent with few streams (the 320x48x32 latent at 4,096 streams, or
-    the 192x16x16 latent at 256 streams) decoded with 16 lanes per stream:
-    the plain 17-ary search against the group form of the learned bracket
-    (one 16-boundary round around the prediction), same bitstream."""
+    the 192x16x16 latent at 256 streams) decoded by lane groups: the plain
+    (L+1)-ary search at the library's automatic L (8 and 16 lanes per stream
+    here) against the group form of the learned bracket (16 lanes, one
+    16-boundary round around the prediction), same bitstream."""
     import torch
     cfgd = synth.CONFIGS[name]
     lat = synth.make_latents(cfgd, backend="torch", device=dev)[0]
@@ -614,7 +615,8 @@ def bracket_few_streams_form(api, synth, dev, name, model, reps=10):
     torch.cuda.synchronize()
     assert torch.equal(dec, lat.symbols) and L.st.tolist() == [0, 0]
     br.close()
-    return {"shape": list(lat.shape), "n": L.n, "streams": L.S, "lanes_per_stream": 16,
+    return {"shape": list(lat.shape), "n": L.n, "streams": L.S,
+            "plain_lanes_per_stream": api.decode_lanes(L.cfg), "bracket_lanes_per_stream": 16,
             "plain_decode_sym_s": L.n / t_plain, "bracket_decode_sym_s": L.n / t_br,
             "plain_decode_ms": round(t_plain * 1e3, 4), "bracket_decode_ms": round(t_br * 1e3, 4),
             "gain": t_plain / t_br, "hit_rate": hits / max(hits + misses, 1),
@@ -899,6 +901,7 @@ def main():
         L = lats[nm]
         bps = 16.0 * float(L.off[-1].item()) / L.n
         forms[nm] = {"shape": list(L.lat.shape), "n": L.n, "streams": L.S,
+                     "decode_lanes_per_stream": api.decode_lanes(L.cfg),
                      "encode_sym_s": L.n / ev[(nm, "encode")],
                      "decode_sym_s": L.n / ev[(nm, "decode")],
                      "bits_per_symbol": bps,

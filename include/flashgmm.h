@@ -369,14 +369,19 @@ int gmm_plan_destroy(gmm_plan* plan);
  * sequential rounds to ceil(log_{lanes+1} N) at the cost of more total
  * evaluations (for latents with few streams); 0 (default) chooses from the
  * stream count: the smallest power of two up to 32 that gives at least
- * 65,536 lanes, except that 16 replaces 32 when it needs no more rounds
- * (without a bracket). With a bracket, 16 or more lanes select the group form
+ * 65,536 lanes, which (without a bracket) is then halved, down to 2, while
+ * the (lanes+1)-ary search needs no more rounds. With a bracket, 16 or more lanes select the group form
  * with 16 lanes per stream (the network's prediction seeds one round that
  * evaluates 16 consecutive boundaries, with a 17-ary search as fallback),
  * 8 lanes the group form with 8 (8 boundaries, 9-ary fallback), fewer the
  * one-lane form (a verified bracket of radius R, then a binary search).
  * Output is identical for every choice. GMM_EINVAL otherwise. */
 int gmm_set_decode_lanes(int32_t lanes);
+
+/* Lanes per stream that a gmm_decode of cfg [host] without a bracket uses
+ * now (the gmm_set_decode_lanes choice, or the automatic one for cfg's
+ * stream count and alphabet); -GMM_EINVAL for an invalid cfg. */
+int gmm_decode_lanes(const gmm_cfg* cfg);
 
 /* Issue priority, 0 (default) to 3, of the wavefronts of later
  * gmm_encode / gmm_decode calls (subset passes and bracket decodes included;

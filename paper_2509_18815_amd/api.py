@@ -85,6 +85,7 @@ _SIGS = {
     "gmm_fast_recip_mismatches": (ctypes.c_int, [_P, _P]),
     "gmm_params_from_raw": (ctypes.c_int, [_I32, _I64, _P, _P, _P, _P, _P]),
     "gmm_set_decode_lanes": (ctypes.c_int, [_I32]),
+    "gmm_decode_lanes": (ctypes.c_int, [_CFG]),
     "gmm_set_wave_priority": (ctypes.c_int, [_I32]),
     "gmm_plan_create": (ctypes.c_int, [_CFG, _I32, _P, _P, _I32, _I32, _P]),
     "gmm_plan_exec": (ctypes.c_int, [_P, _P, _P, _P]),
@@ -296,6 +297,15 @@ def params_from_raw(logits, log_scales, stream=None):
 def set_decode_lanes(lanes: int) -> None:
     """Lanes per stream of later decodes (0 = automatic); output unchanged."""
     _check(lib().gmm_set_decode_lanes(int(lanes)), "set_decode_lanes")
+
+
+def decode_lanes(cfg: Cfg) -> int:
+    """Lanes per stream a plain decode of cfg uses now (the
+    set_decode_lanes choice, or the automatic one)."""
+    L = lib().gmm_decode_lanes(ctypes.byref(cfg))
+    if L < 0:
+        _check(-L, "decode_lanes")
+    return L
 
 
 def set_wave_priority(priority: int) -> None:

@@ -414,18 +414,33 @@ int default_lanes_per_stream(int64_t S) {
   return L;
 }
 
+// Lanes per stream of a plain decode (lanes > 0: the caller's choice).
+int plain_decode_lanes(const gmm_cfg* cfg, int lanes) {
+  const int32_t N = cfg->hi - cfg->lo + 1;
+  int L = (lanes > 0) ? lanes : default_lanes_per_stream(cfg->num_streams);
+  // The automatic choice then halves the group while that needs no more
+  // rounds: a smaller group makes fewer evaluations per symbol, exchanges its
+  // bounds in fewer DPP steps (16 lanes: a DPP row, no LDS) and leaves SIMDs
+  // free for concurrent work. 192x16x16 latent (256 streams, N = 256): 16
+  // lanes 0.145 ms against 32 lanes 0.158 ms; 320x48x32 latent (4,096
+  // streams, N = 511, three rounds at 8 and 16 lanes): 8 lanes 0.135 ms
+  // against 0.150 ms on its own, and 0.388 against 0.39-0.44 ms per plain
+  // step of the two paper-scale latents on two streams.
+  if (lanes <= 0 && L > 2) {
+    const int r = search_rounds_lps(N, L);
+    while (L > 2 && search_rounds_lps(N, L / 2) == r) L >>= 1;
+  }
+  if (cfg->cdf_kind >= 2) L = (L == 1) ? 1 : 16;  // the comparison kinds build L = 1 and 16
+  return L;
+}
+
 int decode_launch(const gmm_cfg* cfg, int64_t n, const uint16_t* bs, int64_t total_words,
                   const int64_t* offsets, const float* w, const float* mu, const float* sg,
                   int32_t* symbols, uint32_t* status, bool fast, hipStream_t st, int lanes,
                   const int32_t* idx, int64_t n_total, int32_t* dev_status) {
   const int64_t S = cfg->num_streams;
   const QCfg q = make_qcfg(cfg);
-  int L = (lanes > 0) ? lanes : default_lanes_per_stream(S);
-  // 16 lanes instead of 32 when they need no more rounds: a 16-lane group is
-  // a DPP row and exchanges its bounds without LDS (192x16x16 latent, 256
-  // streams, N = 256: 0.145 against 0.158 ms)
-  if (lanes <= 0 && L == 32 && search_rounds_lps(q.N, 16) == search_rounds_lps(q.N, 32)) L = 16;
-  if (cfg->cdf_kind >= 2) L = (L == 1) ? 1 : 16;  // the comparison kinds build L = 1 and 16
+  const int L = plain_decode_lanes(cfg, lanes);
   const int rounds = (L == 1) ? search_rounds(q.N) : search_rounds_lps(q.N, L);
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, status, 0u, (int64_t)2);
   if (idx && n > 0)
@@ -489,6 +504,11 @@ int gmm_set_decode_lanes(int32_t lanes) {
   return GMM_OK;
 }
 
+
+int gmm_decode_lanes(const gmm_cfg* cfg) {
+  if (fgmm::check_cfg(cfg, 0)) return -GMM_EINVAL;
+  return fgmm::plain_decode_lanes(cfg, g_lanes_override);
+}
 
 int gmm_set_wave_priority(int32_t priority) {
   if (priority < 0 || priority > 3) return GMM_EINVAL;
