@@ -319,6 +319,17 @@ def kernel_records(root: str, prefixes=("k_", "kb_")) -> list:
     return out
 
 
+def most_called_shapes(records: list) -> list:
+    """Per kernel, the record of its most-called launch shape (the tuned
+    one: the autotuner runs every candidate shape a few times, the chosen
+    one on every call; the other shapes stay in the profile summaries)."""
+    best = {}
+    for r in records:
+        if r["calls"] > best.get(r["kernel"], {}).get("calls", 0):
+            best[r["kernel"]] = r
+    return [r for r in records if best.get(r["kernel"]) is r]
+
+
 def summarize_prof(root: str) -> str:
     """Markdown summary of rocprofv3 CSV output under root/{trace,fetch,write,
     valu}: per (kernel, grid) mean duration, HBM bytes from FETCH_SIZE and
@@ -427,14 +438,9 @@ def form_counters(name: str):
     keep = ("kernel", "grid", "calls", "mean_us", "read_MB", "write_MB", "hbm_GBps",
             "hbm_frac", "valu_issue_frac")
     prefix = {"c3": ("kb_",), "c5": ("kb_",), "c4": ("k_decode_bracket",)}.get(name, ("k",))
-    # per kernel, the launch shape run most often: the tuned one (the
-    # autotuner runs every candidate a few times, the chosen one every call)
-    best = {}
-    for r in rec["kernels"]:
-        if r["kernel"].startswith(prefix) and r["calls"] > best.get(r["kernel"], {}).get("calls", 0):
-            best[r["kernel"]] = r
+    recs = most_called_shapes([r for r in rec["kernels"] if r["kernel"].startswith(prefix)])
     return {"source": os.path.relpath(COUNTERS_FILE, ROOT),
-            "kernels": [{k: r[k] for k in keep if k in r} for r in best.values()]}
+            "kernels": [{k: r[k] for k in keep if k in r} for r in recs]}
 
 
 def time_events(fn, reps, stream):
@@ -796,7 +802,7 @@ def main():
         # bench.py --record-counters <profile dir> <form name>
         allrec = json.load(open(COUNTERS_FILE)) if os.path.exists(COUNTERS_FILE) else {}
         allrec[sys.argv[3]] = {"source_sha": library_source_hash(),
-                               "kernels": kernel_records(sys.argv[2])}
+                               "kernels": most_called_shapes(kernel_records(sys.argv[2]))}
         with open(COUNTERS_FILE, "w") as fh:
             json.dump(allrec, fh, indent=1)
         print(json.dumps(allrec[sys.argv[3]])[:2000])
