@@ -179,11 +179,12 @@ __global__ void __launch_bounds__(kPBlock)
 // by ticket) and dynamic.
 template <int SPL>
 __global__ void __launch_bounds__(kRBlock / SPL)
-    kb_enc_rans_lds(const LatentDesc* __restrict__ desc, int P, const int32_t* __restrict__ items,
+    kb_enc_rans_lds(const LatentDesc* __restrict__ desc, int P, int trash_row,
+                    const int32_t* __restrict__ items,
                     int64_t n_items, int sched, uint32_t* queue,
                     const int32_t* __restrict__ blk_latent, const uint32_t* __restrict__ cf,
                     uint64_t* slots, uint32_t* status) {
-  extern __shared__ uint16_t words[];  // [cap][kRBlock]
+  extern __shared__ uint16_t words[];  // [cap + 1][kRBlock], row cap: trash
   __shared__ int64_t item_sh, excl_sh;
   __shared__ uint32_t tot_a_sh;
   constexpr int T = kRBlock / SPL;
@@ -201,13 +202,14 @@ __global__ void __launch_bounds__(kRBlock / SPL)
     uint32_t xa = 1u << 16, xb = 1u << 16, ca = 0, cb = 0;
     bool zf = false;
     if (SPL == 1) {
-      if (sa < d.S) xa = rans_stream_lds(d.n, d.S, P, sa, lcf, words + threadIdx.x, kRBlock, &ca,
-                                         &zf);
+      if (sa < d.S)
+        xa = rans_stream_lds(d.n, d.S, P, sa, lcf, words + threadIdx.x, kRBlock, trash_row, &ca,
+                             &zf);
     } else if (sa < d.S) {
       // a lane whose second stream lies past S steps its first one twice;
       // the copy's words go to an unused column and are dropped
       rans_stream_lds2(d.n, d.S, P, sa, sb < d.S ? sb : sa, lcf, words + threadIdx.x,
-                       words + threadIdx.x + T, kRBlock, xa, xb, ca, cb, zf);
+                       words + threadIdx.x + T, kRBlock, trash_row, xa, xb, ca, cb, zf);
       if (sb >= d.S) cb = 0;
     }
     (void)zf;  // plans report ranges in phase 1 (no f = 0 words)
@@ -374,7 +376,7 @@ struct Config {
 
 // Largest dynamic LDS of kb_enc_rans_lds (words of a work item's 256
 // streams): streams of up to 300 symbols.
-constexpr int64_t kRansLdsMax = 300 * kRBlock * 2;
+constexpr int64_t kRansLdsMax = (300 + 1) * kRBlock * 2;
 
 bool same_io(const gmm_latent_io& a, const gmm_latent_io& b) {
   return memcmp(&a, &b, sizeof(gmm_latent_io)) == 0;
@@ -506,14 +508,16 @@ int enqueue(gmm_plan* p, const Config& c, hipStream_t st) {
           (c.sched == kFlat) ? p->n_rans_blk
                              : std::min<int64_t>(p->n_rans_blk,
                                                  std::max<int64_t>(1, persist_grid / wpb));
-      const size_t lds = (size_t)(p->cap_max * kRBlock * 2);
+      const size_t lds = (size_t)((p->cap_max + 1) * kRBlock * 2);  // and a trash row
       if (c.spl == 2)
         hipLaunchKernelGGL(kb_enc_rans_lds<2>, dim3((unsigned)grid), dim3(kRBlock / 2), lds, st,
-                           p->d_desc, p->cfg.precision, p->d_rans_items, p->n_rans_blk, c.sched,
+                           p->d_desc, p->cfg.precision, (int)p->cap_max, p->d_rans_items,
+                           p->n_rans_blk, c.sched,
                            queue, p->d_rans_blk, p->d_cf, p->d_slots, p->d_bits);
       else
         hipLaunchKernelGGL(kb_enc_rans_lds<1>, dim3((unsigned)grid), dim3(kRBlock), lds, st,
-                           p->d_desc, p->cfg.precision, p->d_rans_items, p->n_rans_blk, c.sched,
+                           p->d_desc, p->cfg.precision, (int)p->cap_max, p->d_rans_items,
+                           p->n_rans_blk, c.sched,
                            queue, p->d_rans_blk, p->d_cf, p->d_slots, p->d_bits);
       hipLaunchKernelGGL(kb_finalize, dim3((unsigned)((B + 63) / 64)), dim3(64), 0, st,
                          p->d_bits, B, p->d_codes);
@@ -609,7 +613,7 @@ std::vector<Config> candidates(const gmm_plan* p) {
     // words staged in LDS, one pass per item (flat by ticket or dynamic;
     // a static assignment could wait on an item not yet started), one or
     // two streams per lane
-    if (p->cap_max * kRBlock * 2 <= kRansLdsMax && lds_ready()) {
+    if ((p->cap_max + 1) * kRBlock * 2 <= kRansLdsMax && lds_ready()) {
       for (int spl : {1, 2}) {
         v.push_back({1, spl, kFlat, 8, 1});
         for (int w : wpcs) v.push_back({1, spl, kDynamic, w, 1});
@@ -694,7 +698,7 @@ Config default_config(const gmm_plan* p) {
   Config c;
   // encode: words staged in LDS where the streams fit (measured 2-4% faster
   // than the scratch rows on the 64- and 256-latent batches)
-  if (p->op == 0 && p->cap_max * kRBlock * 2 <= kRansLdsMax && lds_ready()) c.lds = 1;
+  if (p->op == 0 && (p->cap_max + 1) * kRBlock * 2 <= kRansLdsMax && lds_ready()) c.lds = 1;
   if (p->op == 1 && !p->bracket) {
     int64_t streams = 0;
     for (int b = 0; b < p->B; ++b) streams += p->S[b];
@@ -978,7 +982,7 @@ int gmm_plan_set_config(gmm_plan* p, const gmm_plan_config* config) {
   if (schedule < kFlat || schedule > kStatic || waves_per_cu < 1 || waves_per_cu > 64)
     return GMM_EINVAL;
   if (lds != 0 && lds != 1) return GMM_EINVAL;
-  if (lds && (p->op != 0 || schedule == kStatic || p->cap_max * kRBlock * 2 > kRansLdsMax ||
+  if (lds && (p->op != 0 || schedule == kStatic || (p->cap_max + 1) * kRBlock * 2 > kRansLdsMax ||
               !lds_ready()))
     return GMM_EINVAL;
   // two streams per lane: the LDS-staged encode pass, or the plain decode

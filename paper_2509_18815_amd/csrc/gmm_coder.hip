@@ -99,10 +99,11 @@ __global__ void __launch_bounds__(kRansBlock)
 // writes offsets[S], flags ENOSPC and writes the call's status code
 // (bits[0]: status bits).
 __global__ void __launch_bounds__(kRansBlock)
-    k_enc_rans_lds(int64_t n, int64_t S, int P, const uint32_t* __restrict__ cf,
+    k_enc_rans_lds(int64_t n, int64_t S, int P, int trash_row,
+                   const uint32_t* __restrict__ cf,
                    int64_t* __restrict__ offsets, uint16_t* __restrict__ bitstream,
                    int64_t capacity, uint64_t* slots, uint32_t* bits, int32_t* dev_status) {
-  extern __shared__ uint16_t words[];  // [cap][kRansBlock]
+  extern __shared__ uint16_t words[];  // [cap + 1][kRansBlock], row cap: trash
   __shared__ int64_t ticket_sh, excl_sh;
   if (threadIdx.x == 0) ticket_sh = (int64_t)atomicAdd(bits + 1, 1u);
   __syncthreads();
@@ -110,7 +111,8 @@ __global__ void __launch_bounds__(kRansBlock)
   const int64_t s = ticket * kRansBlock + threadIdx.x;
   uint32_t cnt = 0, x = 1u << 16;
   bool zf = false;
-  if (s < S) x = rans_stream_lds(n, S, P, s, cf, words + threadIdx.x, kRansBlock, &cnt, &zf);
+  if (s < S)
+    x = rans_stream_lds(n, S, P, s, cf, words + threadIdx.x, kRansBlock, trash_row, &cnt, &zf);
   uint32_t tot;
   const uint32_t len = (s < S) ? cnt + 2u : 0u;
   const uint32_t local = block_excl_scan<kRansBlock>(len, &tot);
@@ -325,7 +327,7 @@ int finish(uint32_t* bits, int32_t* dev_status, hipStream_t st) {
 
 // Largest dynamic LDS of k_enc_rans_lds (words of a workgroup's streams):
 // streams of up to 300 symbols; longer ones take the scratch-row path.
-constexpr int64_t kRansLdsMax = 300 * kRansBlock * 2;
+constexpr int64_t kRansLdsMax = (300 + 1) * kRansBlock * 2;
 
 // Lets k_enc_rans_lds use more than the default dynamic LDS (once).
 bool enc_lds_ready() {
@@ -377,10 +379,10 @@ int encode_launch(const gmm_cfg* cfg, int64_t n, const int32_t* symbols, const f
                            mu, sg, cf, status, nullptr, (int64_t)0, status, nclear);
     });
   }
-  const int64_t lds = L.cap * kRansBlock * 2;
+  const int64_t lds = (L.cap + 1) * kRansBlock * 2;  // the words and a trash row
   if (lds <= kRansLdsMax && enc_lds_ready()) {
     hipLaunchKernelGGL(k_enc_rans_lds, dim3((unsigned)L.nblk), dim3(kRansBlock), (size_t)lds, st,
-                       n, S, cfg->precision, cf, offsets, bitstream, capacity,
+                       n, S, cfg->precision, (int)L.cap, cf, offsets, bitstream, capacity,
                        (uint64_t*)(ws + L.look), status, dev_status);
     return hipGetLastError() == hipSuccess ? GMM_OK : GMM_EDEVICE;
   }

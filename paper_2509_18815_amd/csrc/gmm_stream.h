@@ -336,8 +336,8 @@ __device__ __forceinline__ uint32_t rans_stream(int64_t n, int64_t S, int P, int
 // f = 0.
 __device__ __forceinline__ uint32_t rans_stream_lds(int64_t n, int64_t S, int P, int64_t s,
                                                     const uint32_t* __restrict__ cf,
-                                                    uint16_t* col, int stride, uint32_t* count,
-                                                    bool* zero_f) {
+                                                    uint16_t* col, int stride, int trash_row,
+                                                    uint32_t* count, bool* zero_f) {
   const int64_t ns = stream_len(n, S, s);
   uint32_t x = 1u << 16;
   uint32_t cnt = 0;
@@ -366,12 +366,17 @@ __device__ __forceinline__ uint32_t rans_stream_lds(int64_t n, int64_t S, int P,
     }
 #pragma unroll
     for (int d = 0; d < kDepth; ++d) {
-      if (p - d < 0) break;
+      // every step of the block runs (no branch per step): a step past the
+      // stream's start leaves the state as it is, and a step that emits no
+      // word stores its word to the trash row
+      const bool live = p - d >= 0;
       bool emit;
-      uint32_t word;
-      zf = zf || (cur[d] & 0xFFFFu) == 0u;
-      rans_put(x, cur[d], P, shift, emit, word);
-      if (emit) col[cnt * stride] = (uint16_t)word;
+      uint32_t word, xn = x;
+      rans_put(xn, cur[d], P, shift, emit, word);
+      emit = emit && live;
+      zf = zf || (live && (cur[d] & 0xFFFFu) == 0u);
+      col[(emit ? (int)cnt : trash_row) * stride] = (uint16_t)word;
+      x = live ? xn : x;
       cnt += emit ? 1u : 0u;
     }
   }
@@ -387,7 +392,8 @@ __device__ __forceinline__ uint32_t rans_stream_lds(int64_t n, int64_t S, int P,
 __device__ __forceinline__ void rans_stream_lds2(int64_t n, int64_t S, int P, int64_t sa,
                                                  int64_t sb, const uint32_t* __restrict__ cf,
                                                  uint16_t* cola, uint16_t* colb, int stride,
-                                                 uint32_t& xa, uint32_t& xb, uint32_t& ca,
+                                                 int trash_row, uint32_t& xa, uint32_t& xb,
+                                                 uint32_t& ca,
                                                  uint32_t& cb, bool& zero_f) {
   const int64_t na = stream_len(n, S, sa), nb = stream_len(n, S, sb);
   const int64_t nmax = na > nb ? na : nb;
@@ -425,23 +431,20 @@ __device__ __forceinline__ void rans_stream_lds2(int64_t n, int64_t S, int P, in
 #pragma unroll
     for (int d = 0; d < kDepth; ++d) {
       const int64_t q = p - d;
-      if (q < 0) break;
-      if (q < na) {
-        bool emit;
-        uint32_t word;
-        zf = zf || (cura[d] & 0xFFFFu) == 0u;
-        rans_put(xa, cura[d], P, shift, emit, word);
-        if (emit) cola[ca * stride] = (uint16_t)word;
-        ca += emit ? 1u : 0u;
-      }
-      if (q < nb) {
-        bool emit;
-        uint32_t word;
-        zf = zf || (curb[d] & 0xFFFFu) == 0u;
-        rans_put(xb, curb[d], P, shift, emit, word);
-        if (emit) colb[cb * stride] = (uint16_t)word;
-        cb += emit ? 1u : 0u;
-      }
+      const bool la = q >= 0 && q < na, lb = q >= 0 && q < nb;
+      bool ea, eb;
+      uint32_t wa, wb, xna = xa, xnb = xb;
+      rans_put(xna, cura[d], P, shift, ea, wa);
+      rans_put(xnb, curb[d], P, shift, eb, wb);
+      ea = ea && la;
+      eb = eb && lb;
+      zf = zf || (la && (cura[d] & 0xFFFFu) == 0u) || (lb && (curb[d] & 0xFFFFu) == 0u);
+      cola[(ea ? (int)ca : trash_row) * stride] = (uint16_t)wa;
+      colb[(eb ? (int)cb : trash_row) * stride] = (uint16_t)wb;
+      xa = la ? xna : xa;
+      xb = lb ? xnb : xb;
+      ca += ea ? 1u : 0u;
+      cb += eb ? 1u : 0u;
     }
   }
   zero_f = zf;
