@@ -153,6 +153,38 @@ def test_decode_lanes_per_stream_bit_exact(api, orc, lanes):
         api.set_decode_lanes(0)
 
 
+@pytest.mark.parametrize("lo,hi", [(4194049, 4194304), (-4194304, -4193794)])
+@pytest.mark.parametrize("lanes", [0, 1])
+def test_far_support_bit_exact(api, orc, lo, hi, lanes):
+    """Alphabets at the contract's limit |lo|, |hi| <= 2^22 (256 symbols
+    ending at 2^22, 511 starting at -2^22; with one lane per stream the
+    straight-line 8- and 9-round searches), means spread over the support:
+    bitstream, offsets and symbols equal the oracle's."""
+    rng = np.random.default_rng(abs(lo) % 997 + lanes)
+    n, S, K, P = 20000, 64, 3, 16
+    w, mu, sig = synth.random_params(rng, n, K)
+    centre = np.float32((lo + hi) / 2)
+    mu = np.ascontiguousarray((mu * np.float32(20.0) + centre).astype(np.float32))
+    sym = np.clip(np.rint(mu[0] + sig[0] * rng.normal(size=n)), lo, hi).astype(np.int32)
+    sym[:2] = [lo, hi]
+    ocfg = orc.make_cfg(K, lo, hi, P, S, 0)
+    st, obs, ooff = orc.encode(ocfg, sym, w, mu, sig)
+    assert st == orc.OK
+    cfg = api.make_cfg(K, lo, hi, P, S, 0)
+    dsym, dw, dm, ds = dev(sym), dev(w), dev(mu), dev(sig)
+    bs, off = api.encode(dsym, dw, dm, ds, lo, hi, P, S)
+    assert np.array_equal(off.cpu().numpy(), ooff)
+    assert np.array_equal(u16(bs), obs)
+    api.set_decode_lanes(lanes)
+    try:
+        assert api.decode_lanes(cfg) == (lanes or {256: 16, 511: 32}[hi - lo + 1])
+        dec = torch.empty(n, dtype=torch.int32, device="cuda")
+        assert api.decode_into(cfg, bs, off, dw, dm, ds, dec) == api.OK
+    finally:
+        api.set_decode_lanes(0)
+    assert np.array_equal(dec.cpu().numpy(), sym)
+
+
 @pytest.mark.parametrize("name", ["c1", "c2a"])
 def test_workload_bit_exact(api, orc, name):
     cfgd = synth.CONFIGS[name]

@@ -89,6 +89,27 @@ def _params(K, s_logit, s_mu, smax, n, seed):
 @pytest.mark.parametrize("kind", [0, 1])
 def test_oracle_mixture_against_textbook(orc, name, K, lo, hi, s_logit, s_mu, smax, n, kind):
     w, mu, sig = _params(K, s_logit, s_mu, smax, n, 1000 + K + hi + kind)
+    _check_against_textbook(orc, name, w, mu, sig, K, lo, hi, kind)
+
+
+# supports at the contract's limit |lo|, |hi| <= 2^22: 256 symbols ending
+# at 2^22 and 511 starting at -2^22
+FAR = [(4194049, 4194304), (-4194304, -4193794)]
+
+
+@pytest.mark.parametrize("lo,hi", FAR)
+@pytest.mark.parametrize("kind", [0, 1])
+def test_oracle_far_support_against_textbook(orc, lo, hi, kind):
+    """The same check where the boundaries lo + j - 1/2 are half-integers
+    near 2^22 (still exact in binary32, whose unit there is 1/2), with the
+    means spread over the support so that the mixture has mass in it."""
+    w, mu, sig = _params(3, 1.0, 2.0, 20.0, 900, 4242 + kind + (lo > 0))
+    centre = np.float32((lo + hi) / 2)
+    mu = np.ascontiguousarray((mu * np.float32(20.0) + centre).astype(np.float32))
+    _check_against_textbook(orc, f"[{lo}, {hi}]", w, mu, sig, 3, lo, hi, kind)
+
+
+def _check_against_textbook(orc, name, w, mu, sig, K, lo, hi, kind):
     cfg = orc.make_cfg(K, lo, hi, 16, 1, kind)
     F = orc.F_table(cfg, w, mu, sig).astype(np.float64)
     phi = phi_as_textbook if kind == 0 else phi_logistic_textbook
