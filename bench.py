@@ -1019,7 +1019,7 @@ def main():
         forms["c4_bracket"] = bracket_single_form(api, synth, dev, m4)
         forms["c4_bracket"]["counters"] = form_counters("c4")
         # the same model (same parameter distributions and support) on the
-        # Kodak-size latent, whose 4,096 streams decode with 16 lanes each
+        # Kodak-size latent, whose 4,096 streams decode by lane groups
         forms["c2a_bracket"] = bracket_few_streams_form(api, synth, dev, "c2a", m4)
         forms["step_learned_bracket"] = learned_step_form(api, lats, m4, step, args.steps,
                                                           args.warmup, value, dev)

@@ -248,8 +248,9 @@ def test_bracket_decode_matches_oracle_on_corruption(api, orc, trained, lanes):
 
 @pytest.mark.parametrize("lanes", [0, 8], indirect=True)
 def test_group_bracket_decode_kodak_latent(api, orc, trained, lanes):
-    """The 320x48x32 latent at 4,096 streams decodes with 16 lanes per stream:
-    the group form of the bracket (matrix-core inference for four streams
+    """The 320x48x32 latent at 4,096 streams with a bracket decodes by lane
+    groups (16 lanes per stream by default, or 8): the group form of the
+    bracket (matrix-core inference for four streams
     per wavefront, one 16-boundary window round) is bit-identical to the
     plain decode; a trained model hits on nearly every symbol (which also
     checks the 16x16x32 operand layout: a wrong layout predicts noise); an
