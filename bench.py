@@ -443,6 +443,73 @@ def form_counters(name: str):
             "kernels": [{k: r[k] for k in keep if k in r} for r in recs]}
 
 
+class TimingEvent:
+    """A HIP event for timing only, created with hipEventDisableSystemFence
+    in the HIP runtime that torch loaded (the one the library's calls use).
+    A default event is recorded with a system-scope release: the L2 is
+    written back after the preceding kernel before the stream moves on. Two
+    such events around the 4K decode were measured to add ~20 us to each
+    step (0.407-0.415 against 0.383-0.395 ms without events) and ~10 us to
+    the decode they bracket; these events add neither (0.391-0.394 ms)."""
+    DISABLE_SYSTEM_FENCE = 0x20000000
+    _hip = None
+
+    @classmethod
+    def runtime(cls):
+        """The process's libamdhip64 (None if it cannot be found)."""
+        if cls._hip is None:
+            import ctypes
+            path = None
+            try:
+                for line in open("/proc/self/maps"):
+                    f = line.split()[-1]
+                    if os.path.basename(f).startswith("libamdhip64.so"):
+                        path = f
+                        break
+            except OSError:
+                pass
+            cls._hip = ctypes.CDLL(path) if path else False
+        return cls._hip or None
+
+    def __init__(self):
+        import ctypes
+        hip = self.runtime()
+        self.ev = ctypes.c_void_p()
+        if hip is None or hip.hipEventCreateWithFlags(
+                ctypes.byref(self.ev), ctypes.c_uint(self.DISABLE_SYSTEM_FENCE)) != 0:
+            raise RuntimeError("hipEventCreateWithFlags failed")
+
+    def record(self, stream):
+        import ctypes
+        if self.runtime().hipEventRecord(self.ev, ctypes.c_void_p(stream.cuda_stream)) != 0:
+            raise RuntimeError("hipEventRecord failed")
+
+    def elapsed_time(self, end) -> float:
+        """Milliseconds from this event to end (both completed)."""
+        import ctypes
+        ms = ctypes.c_float()
+        if self.runtime().hipEventElapsedTime(ctypes.byref(ms), self.ev, end.ev) != 0:
+            raise RuntimeError("hipEventElapsedTime failed")
+        return ms.value
+
+    def destroy(self):
+        if self.ev:
+            self.runtime().hipEventDestroy(self.ev)
+            self.ev = None
+
+
+def timing_event_pairs(count):
+    """count pairs of fence-free timing events, or of torch events where the
+    HIP runtime cannot be reached; returns (pairs, kind)."""
+    import torch
+    try:
+        return [(TimingEvent(), TimingEvent()) for _ in range(count)], \
+            "hipEventDisableSystemFence"
+    except (RuntimeError, OSError, AttributeError):
+        return [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                for _ in range(count)], "torch.cuda.Event (system-scope release)"
+
+
 def time_events(fn, reps, stream):
     import torch
     a = torch.cuda.Event(enable_timing=True)
@@ -863,7 +930,9 @@ def main():
     side = torch.cuda.Stream()  # default priority
 
     # HIP events around the 4K-latent decode (the dominant kernel) on the
-    # launch stream, recorded inside the timed steps
+    # launch stream, recorded inside the timed steps; created beforehand,
+    # fence-free (TimingEvent)
+    ev_pool, ev_kind = timing_event_pairs(args.steps)
     ev_pairs = []
 
     def step(record=False, kodak_decode=None):
@@ -878,8 +947,7 @@ def main():
             (kodak_decode or lats["c2a"].decode)()
         lats["c2b"].encode()
         if record:
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
+            a, b = ev_pool[len(ev_pairs)]
             a.record(stream)
             lats["c2b"].decode()
             b.record(stream)
@@ -904,6 +972,10 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     dec_in_steps = sum(a.elapsed_time(b) for a, b in ev_pairs) / 1e3 / len(ev_pairs)
+    for pair in ev_pool:
+        for e in pair:
+            if isinstance(e, TimingEvent):
+                e.destroy()
     for nm in names:
         lats[nm].verify()
     n_total = sum(lats[nm].n for nm in names)
@@ -970,6 +1042,7 @@ def main():
                 "flops_per_symbol": decode_flops_per_symbol(K, N),
                 "symbols_per_launch": big.n,
                 "launch_ms": round(dec_t * 1e3, 4),
+                "launch_timing_events": ev_kind,
                 "launch_ms_isolated": round(ev[("c2b", "decode")] * 1e3, 4),
                 # the same launch back to back on its own (no co-running
                 # Kodak-latent kernels), for comparison
