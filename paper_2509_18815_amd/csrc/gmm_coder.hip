@@ -462,6 +462,8 @@ int decode_launch(const gmm_cfg* cfg, int64_t n, const uint16_t* bs, int64_t tot
                     offsets, w, mu, sg, symbols, status, dev_status, st);
     return hipGetLastError() == hipSuccess ? GMM_OK : GMM_EDEVICE;
   }
+  // buffer resources for the whole-latent decode when its offsets fit 32 bits
+  const bool buf = !idx && buffer_offsets_fit(cfg->K, n, S, total_words);
   dispatch(cfg->K, cfg->cdf_kind, fast, [&](auto Kc, auto kc, auto fc) {
     constexpr int K_ = decltype(Kc)::value, KI = decltype(kc)::value;
     constexpr bool F = decltype(fc)::value;
@@ -470,6 +472,10 @@ int decode_launch(const gmm_cfg* cfg, int64_t n, const uint16_t* bs, int64_t tot
     hipLaunchKernelGGL((k_decode<K_, KI, F, LL, true>), grid, block, 0, st, q, cfg->precision,  \
                        rounds, n, S, bs, total_words, offsets, w, mu, sg, symbols, status,      \
                        dev_status, idx, n_total);                                               \
+  else if (buf)                                                                                 \
+    hipLaunchKernelGGL((k_decode<K_, KI, F, LL, false, true>), grid, block, 0, st, q,           \
+                       cfg->precision, rounds, n, S, bs, total_words, offsets, w, mu, sg,       \
+                       symbols, status, dev_status, nullptr, (int64_t)0);                       \
   else                                                                                          \
     hipLaunchKernelGGL((k_decode<K_, KI, F, LL, false>), grid, block, 0, st, q, cfg->precision, \
                        rounds, n, S, bs, total_words, offsets, w, mu, sg, symbols, status,      \

@@ -77,7 +77,7 @@ __global__ void k_enc_cdf(fgmm::QCfg q, int64_t n, const int32_t* __restrict__ s
 // collects the status bits, status[1] counts finished workgroups (both
 // zeroed before the launch); the last workgroup writes the call's status
 // code to dev_status when given.
-template <int K, int kKind, bool kFast, int L, bool kGather = false>
+template <int K, int kKind, bool kFast, int L, bool kGather = false, bool kBuf = false>
 __global__ void __launch_bounds__(256)
     k_decode(fgmm::QCfg q, int P, int rounds, int64_t n, int64_t S, const uint16_t* __restrict__ bs,
              int64_t total_words, const int64_t* __restrict__ offsets,
@@ -92,7 +92,7 @@ __global__ void __launch_bounds__(256)
   const int g = (int)(gt % L);
   // groups never straddle the S boundary (S * L lanes, L divides 64)
   if (s < S) {
-    const bool bad = decode_stream<K, kKind, kFast, L, kGather, L == 1>(
+    const bool bad = decode_stream<K, kKind, kFast, L, kGather, L == 1, kBuf>(
         q, P, rounds, n, S, s, g, bs, total_words, offsets, w, mu, sg, sym, idx, n_total);
     if (bad && g == 0) atomicOr(status, kStCorrupt);
   }

@@ -18,6 +18,20 @@ __device__ __forceinline__ int64_t stream_len(int64_t n, int64_t S, int64_t s) {
   return (s < n) ? (n - 1 - s) / S + 1 : 0;
 }
 
+// Third word of a raw buffer resource (stride 0, 32-bit elements, range
+// checked against the byte count) on gfx9-family parts.
+constexpr int kRsrcWord3 = 0x00020000;
+
+// Whether every byte offset of decode_stream's buffer path fits the
+// resources' 32-bit range: the K planes of n elements, positions up to
+// three steps past a stream's last element (clamped, but counted before
+// the clamp), the bitstream's words and the symbols.
+__host__ __device__ inline bool buffer_offsets_fit(int K, int64_t n, int64_t S,
+                                                   int64_t total_words) {
+  const int64_t lim = 0xFFFFFFFFll;
+  return n >= 0 && S >= 1 && 4 * ((int64_t)K * n + 4 * S) <= lim && 2 * (total_words + 1) <= lim;
+}
+
 // Element of a subset pass, clamped into the latent so that an invalid
 // index (reported as EINVAL by the pass's index check) never reads or
 // writes outside the buffers.
@@ -640,7 +654,14 @@ __device__ __forceinline__ float opaque_copy(float v) {
 // n_total elements: pass position i reads its parameters at element idx[i]
 // of the [K][n_total] planes and writes its symbol to sym[idx[i]].
 // kStraight selects the straight-line binary search (search_bs).
-template <int K, int kKind, bool kFast, int L, bool kGather = false, bool kStraight = false>
+// With kBuf the parameters, the refill words and the symbols go through
+// buffer resources with 32-bit byte offsets: one offset per step for all
+// 3K parameter loads (the plane rows at constant scalar offsets k n 4), no
+// 64-bit address arithmetic, and no clamp for the refill word (a word past
+// the bitstream reads 0 by the resource's range check). The caller selects
+// it only when every offset fits: buffer_offsets_fit below.
+template <int K, int kKind, bool kFast, int L, bool kGather = false, bool kStraight = false,
+          bool kBuf = false>
 __device__ __forceinline__ bool decode_stream(const QCfg& q, int P, int rounds, int64_t n,
                                               int64_t S, int64_t s, int g,
                                               const uint16_t* __restrict__ bs, int64_t total_words,
@@ -679,6 +700,23 @@ __device__ __forceinline__ bool decode_stream(const QCfg& q, int P, int rounds, 
   // so the number of loads per step is fixed and the wait counts stay exact.
   constexpr int kRing = (L == 1) ? 3 : 2;
   const int64_t last = ns - 1;
+  static_assert(!(kBuf && kGather), "the buffer path reads the planes in stream order");
+  [[maybe_unused]] __amdgpu_buffer_rsrc_t bw_, bm_, bsg_, bbs_, bsym_;
+  [[maybe_unused]] uint32_t off_next = 0, off_last = 0, plane = 0;
+  [[maybe_unused]] uint32_t ro[kRing] = {};
+  if constexpr (kBuf) {
+    const int nb = (int)(uint32_t)(K * n * 4);
+    bw_ = __builtin_amdgcn_make_buffer_rsrc((void*)w, (short)0, nb, kRsrcWord3);
+    bm_ = __builtin_amdgcn_make_buffer_rsrc((void*)mu, (short)0, nb, kRsrcWord3);
+    bsg_ = __builtin_amdgcn_make_buffer_rsrc((void*)sg, (short)0, nb, kRsrcWord3);
+    bbs_ = __builtin_amdgcn_make_buffer_rsrc((void*)bs, (short)0,
+                                             (int)(uint32_t)(total_words * 2), kRsrcWord3);
+    bsym_ = __builtin_amdgcn_make_buffer_rsrc((void*)sym, (short)0, (int)(uint32_t)(n * 4),
+                                              kRsrcWord3);
+    plane = (uint32_t)(n * 4);
+    off_next = (uint32_t)s * 4u;  // the element of position 0
+    off_last = (uint32_t)(s + last * S) * 4u;
+  }
   auto elem_at = [&](int64_t p) -> int64_t {
     const int64_t pp = p < last ? p : last;
     return kGather ? gather_index(idx, s + pp * S, n_total) : s + pp * S;
@@ -712,7 +750,12 @@ __device__ __forceinline__ bool decode_stream(const QCfg& q, int P, int rounds, 
         else
           j = search_group<K, kKind, kFast, L>(e, q, rounds, slot, g, gbase, gmask, 0, q.N, cl,
                                                ch);
-        if (g == 0) sym[rg[d]] = q.lo + j;
+        if constexpr (kBuf) {
+          if (g == 0)
+            __builtin_amdgcn_raw_buffer_store_b32((uint32_t)(q.lo + j), bsym_, ro[d], 0, 0);
+        } else {
+          if (g == 0) sym[rg[d]] = q.lo + j;
+        }
       }
       // State update and refill outside the branch, as selects: the word is
       // then used on every path, which keeps its load where it is issued.
@@ -723,10 +766,29 @@ __device__ __forceinline__ bool decode_stream(const QCfg& q, int P, int rounds, 
       x = live ? xr : x;
       bad = bad || (refill && !have);
       ptr += (refill && have) ? 1 : 0;
-      nword = bs[ptr < b ? ptr : b - 1];
-      asm volatile("" ::: "memory");  // keep the word's load ahead of the ring's
-      rg[d] = elem_at(p + kRing);
-      load_raw<K>(w, mu, sg, np, rg[d], rw[d], rm[d], rs[d]);
+      if constexpr (kBuf) {
+        // ptr <= b <= total_words: a word past the bitstream reads 0
+        nword = __builtin_amdgcn_raw_buffer_load_b16(bbs_, (uint32_t)ptr * 2u, 0, 0);
+        asm volatile("" ::: "memory");  // keep the word's load ahead of the ring's
+        // the element of position p + kRing, clamped to the stream's last
+        const uint32_t o = off_next < off_last ? off_next : off_last;
+        ro[d] = o;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          rw[d][k] = __builtin_bit_cast(
+              float, __builtin_amdgcn_raw_buffer_load_b32(bw_, o, k * plane, 0));
+          rm[d][k] = __builtin_bit_cast(
+              float, __builtin_amdgcn_raw_buffer_load_b32(bm_, o, k * plane, 0));
+          rs[d][k] = __builtin_bit_cast(
+              float, __builtin_amdgcn_raw_buffer_load_b32(bsg_, o, k * plane, 0));
+        }
+        off_next += (uint32_t)S * 4u;
+      } else {
+        nword = bs[ptr < b ? ptr : b - 1];
+        asm volatile("" ::: "memory");  // keep the word's load ahead of the ring's
+        rg[d] = elem_at(p + kRing);
+        load_raw<K>(w, mu, sg, np, rg[d], rw[d], rm[d], rs[d]);
+      }
     }
   }
   return bad || x != (1u << 16) || ptr != b;
