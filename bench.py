@@ -420,7 +420,7 @@ COUNTERS_FILE = os.path.join(ROOT, "profiles", "kernel_counters.json")
 # the oracle's longer CPU legs, written by a run with --cpu-baseline-legs
 CPU_LEGS_FILE = os.path.join(ROOT, "profiles", "oracle_cpu_legs.json")
 # the dominant kernel: plain A&S decode, K=3, one lane per stream, direct indexing
-DOMINANT_KERNEL = "k_decode<3, 0, true, 1, false>"
+DOMINANT_KERNEL = "k_decode<3, 0, true, 1, false, true>"
 
 
 def progress(msg: str) -> None:
