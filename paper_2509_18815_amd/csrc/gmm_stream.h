@@ -733,15 +733,24 @@ __device__ __forceinline__ bool decode_stream(const QCfg& q, int P, int rounds, 
       const uint32_t slot = x & mask;
       uint32_t cl = 0, ch = q.M;
       if (live) {
-        // Copies that the register allocator cannot merge with the ring
-        // slot: the slot keeps one register set, and the wait for its loads
-        // lands here instead of at the loop's back edge.
+        // With 64-bit addresses: copies that the register allocator cannot
+        // merge with the ring slot, so that the slot keeps one register set
+        // and the wait for its loads lands here instead of at the loop's
+        // back edge. With buffer loads plain copies measured faster (4K
+        // decode 268-270 -> 262-265 us, 8-lane decode of the 4,096-stream
+        // latent 124.3-125.3 -> 121.8-122.0 us).
         float cw[K], cm[K], cs[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-          cw[k] = opaque_copy(rw[d][k]);
-          cm[k] = opaque_copy(rm[d][k]);
-          cs[k] = opaque_copy(rs[d][k]);
+          if constexpr (kBuf) {
+            cw[k] = rw[d][k];
+            cm[k] = rm[d][k];
+            cs[k] = rs[d][k];
+          } else {
+            cw[k] = opaque_copy(rw[d][k]);
+            cm[k] = opaque_copy(rm[d][k]);
+            cs[k] = opaque_copy(rs[d][k]);
+          }
         }
         const Elem<K> e = make_elem<K, kFast, kKind>(q, cw, cm, cs);
         int32_t j;
