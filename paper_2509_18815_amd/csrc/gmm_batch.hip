@@ -257,7 +257,11 @@ __global__ void __launch_bounds__(kRBlock / SPL)
 }
 
 // Work item = (latent, first stream) of 64/L streams; one wavefront each.
-template <int K, int kKind, bool kFast, int L>
+// With kBuf (every latent's offsets fit 32 bits) decode_stream's buffer
+// path; the item index is wavefront-uniform (read from the first lane into
+// a scalar register), so the latent's descriptor and the buffer resources
+// built from it stay scalar.
+template <int K, int kKind, bool kFast, int L, bool kBuf = false>
 __global__ void __launch_bounds__(64)
     kb_decode(const LatentDesc* __restrict__ desc, QCfg q, int P, int rounds,
               const int2* __restrict__ items, int64_t n_items, int sched, uint32_t* queue,
@@ -269,7 +273,7 @@ __global__ void __launch_bounds__(64)
     if (sched == kDynamic) {
       uint32_t v = 0;
       if (lane == 0) v = atomicAdd(queue, 1u);
-      item = (int64_t)__shfl(v, 0, 64);
+      item = (int64_t)__builtin_amdgcn_readfirstlane(v);
     } else {
       item = it;
     }
@@ -279,9 +283,8 @@ __global__ void __launch_bounds__(64)
     const int64_t s = (int64_t)t.y + lane / L;
     const int g = lane % L;
     if (s < d.S) {
-      const bool bad = decode_stream<K, kKind, kFast, L>(q, P, rounds, d.n, d.S, s, g, d.bs,
-                                                         d.words, d.offsets, d.w, d.mu, d.sg,
-                                                         d.dec);
+      const bool bad = decode_stream<K, kKind, kFast, L, false, false, kBuf>(
+          q, P, rounds, d.n, d.S, s, g, d.bs, d.words, d.offsets, d.w, d.mu, d.sg, d.dec);
       if (bad && g == 0) atomicOr(&status[t.x], kStCorrupt);
     }
     if (sched == kFlat) break;
@@ -412,6 +415,9 @@ struct gmm_plan {
   uint32_t *d_cf = nullptr, *d_xfin = nullptr, *d_count = nullptr, *d_local = nullptr;
   uint16_t* d_scratch = nullptr;
   int64_t *d_blk_total = nullptr, *d_blk_pre = nullptr;
+  // decode: whether every latent's offsets fit decode_stream's buffer path
+  // (set from the buffers of the latest execution; a change recaptures)
+  bool buf = false;
   // decode items (for the chosen lanes and streams per lane)
   int2* d_items = nullptr;
   int64_t n_items = 0;
@@ -570,9 +576,14 @@ int enqueue(gmm_plan* p, const Config& c, hipStream_t st) {
         constexpr int K_ = decltype(Kc)::value, KI = decltype(kc)::value;
         constexpr bool F = decltype(fc)::value;
 #define FG_BDEC(LL)                                                                        \
-  hipLaunchKernelGGL((kb_decode<K_, KI, F, LL>), dim3((unsigned)grid), dim3(64), 0, st,    \
-                     p->d_desc, p->q, p->cfg.precision, rounds, p->d_items, p->n_items,     \
-                     c.sched, queue, p->d_bits)
+  if (p->buf)                                                                              \
+    hipLaunchKernelGGL((kb_decode<K_, KI, F, LL, true>), dim3((unsigned)grid), dim3(64), 0, \
+                       st, p->d_desc, p->q, p->cfg.precision, rounds, p->d_items,          \
+                       p->n_items, c.sched, queue, p->d_bits);                             \
+  else                                                                                     \
+    hipLaunchKernelGGL((kb_decode<K_, KI, F, LL>), dim3((unsigned)grid), dim3(64), 0, st,  \
+                       p->d_desc, p->q, p->cfg.precision, rounds, p->d_items, p->n_items,  \
+                       c.sched, queue, p->d_bits)
         switch (L) {
           case 1: FG_BDEC(1); break;
           case 2: FG_BDEC(2); break;
@@ -929,6 +940,18 @@ int gmm_plan_exec(gmm_plan* p, const gmm_latent_io* io, int32_t* dev_status, voi
                        hipMemcpyHostToDevice, st) != hipSuccess)
       return GMM_EDEVICE;
     p->last_io.assign(io, io + p->B);
+    if (p->op == 1) {
+      bool fit = true;
+      for (int b = 0; b < p->B; ++b)
+        fit = fit && buffer_offsets_fit(p->cfg.K, p->n[b], p->S[b], io[b].words);
+      if (fit != p->buf) {  // the captured graph launches the other decode kernel
+        p->buf = fit;
+        if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+        if (p->graph) (void)hipGraphDestroy(p->graph);
+        p->gexec = nullptr;
+        p->graph = nullptr;
+      }
+    }
   }
   int r;
   if (!p->tuned) {
