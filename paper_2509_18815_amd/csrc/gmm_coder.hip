@@ -98,6 +98,7 @@ __global__ void __launch_bounds__(kRansBlock)
 // for its per-stream shuffles). The workgroup holding the last streams
 // writes offsets[S], flags ENOSPC and writes the call's status code
 // (bits[0]: status bits).
+template <bool kBuf>
 __global__ void __launch_bounds__(kRansBlock)
     k_enc_rans_lds(int64_t n, int64_t S, int P, int trash_row,
                    const uint32_t* __restrict__ cf,
@@ -112,7 +113,8 @@ __global__ void __launch_bounds__(kRansBlock)
   uint32_t cnt = 0, x = 1u << 16;
   bool zf = false;
   if (s < S)
-    x = rans_stream_lds(n, S, P, s, cf, words + threadIdx.x, kRansBlock, trash_row, &cnt, &zf);
+    x = rans_stream_lds<kBuf>(n, S, P, s, cf, words + threadIdx.x, kRansBlock, trash_row, &cnt,
+                              &zf);
   uint32_t tot;
   const uint32_t len = (s < S) ? cnt + 2u : 0u;
   const uint32_t local = block_excl_scan<kRansBlock>(len, &tot);
@@ -331,7 +333,10 @@ constexpr int64_t kRansLdsMax = (300 + 1) * kRansBlock * 2;
 
 // Lets k_enc_rans_lds use more than the default dynamic LDS (once).
 bool enc_lds_ready() {
-  static const bool ok = hipFuncSetAttribute((const void*)k_enc_rans_lds,
+  static const bool ok = hipFuncSetAttribute((const void*)k_enc_rans_lds<false>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)kRansLdsMax) == hipSuccess &&
+                         hipFuncSetAttribute((const void*)k_enc_rans_lds<true>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize,
                                              (int)kRansLdsMax) == hipSuccess;
   return ok;
@@ -359,6 +364,8 @@ int encode_launch(const gmm_cfg* cfg, int64_t n, const int32_t* symbols, const f
   // writes them), else by a fill kernel first
   const int64_t nclear = (L.look + 8 * L.nblk) / 4;
   const bool clear_in_cdf = n > 0 && !idx && cfg->cdf_kind < 2;
+  // buffer resources for the whole-latent encode when its offsets fit 32 bits
+  const bool buf = !idx && encode_offsets_fit(cfg->K, n, S);
   if (!clear_in_cdf)
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((nclear + 255) / 256)), dim3(256), 0, st,
                        status, 0u, nclear);
@@ -374,6 +381,9 @@ int encode_launch(const gmm_cfg* cfg, int64_t n, const int32_t* symbols, const f
       if (idx)
         hipLaunchKernelGGL((k_enc_cdf<K_, KI, F, true>), grid, block, 0, st, q, n, symbols, w,
                            mu, sg, cf, status, idx, n_total);
+      else if (buf)
+        hipLaunchKernelGGL((k_enc_cdf<K_, KI, F, false, true>), grid, block, 0, st, q, n,
+                           symbols, w, mu, sg, cf, status, nullptr, (int64_t)0, status, nclear);
       else
         hipLaunchKernelGGL((k_enc_cdf<K_, KI, F, false>), grid, block, 0, st, q, n, symbols, w,
                            mu, sg, cf, status, nullptr, (int64_t)0, status, nclear);
@@ -381,9 +391,14 @@ int encode_launch(const gmm_cfg* cfg, int64_t n, const int32_t* symbols, const f
   }
   const int64_t lds = (L.cap + 1) * kRansBlock * 2;  // the words and a trash row
   if (lds <= kRansLdsMax && enc_lds_ready()) {
-    hipLaunchKernelGGL(k_enc_rans_lds, dim3((unsigned)L.nblk), dim3(kRansBlock), (size_t)lds, st,
-                       n, S, cfg->precision, (int)L.cap, cf, offsets, bitstream, capacity,
-                       (uint64_t*)(ws + L.look), status, dev_status);
+    if (buf)
+      hipLaunchKernelGGL(k_enc_rans_lds<true>, dim3((unsigned)L.nblk), dim3(kRansBlock),
+                         (size_t)lds, st, n, S, cfg->precision, (int)L.cap, cf, offsets,
+                         bitstream, capacity, (uint64_t*)(ws + L.look), status, dev_status);
+    else
+      hipLaunchKernelGGL(k_enc_rans_lds<false>, dim3((unsigned)L.nblk), dim3(kRansBlock),
+                         (size_t)lds, st, n, S, cfg->precision, (int)L.cap, cf, offsets,
+                         bitstream, capacity, (uint64_t*)(ws + L.look), status, dev_status);
     return hipGetLastError() == hipSuccess ? GMM_OK : GMM_EDEVICE;
   }
   // streams too long for LDS: words through the scratch rows, then k_pack

@@ -53,7 +53,7 @@ __global__ void k_inverse(fgmm::QCfg q, int rounds, int64_t n, const float* __re
 // the first workgroup also zeroes clear[0 .. nclear) (the call's status
 // words and the rANS pass's look-back slots, used only by the kernels
 // after this one), which saves a launch.
-template <int K, int kKind, bool kFast, bool kGather = false>
+template <int K, int kKind, bool kFast, bool kGather = false, bool kBuf = false>
 __global__ void k_enc_cdf(fgmm::QCfg q, int64_t n, const int32_t* __restrict__ sym,
                           const float* __restrict__ w, const float* __restrict__ mu,
                           const float* __restrict__ sg, uint32_t* __restrict__ cf,
@@ -69,7 +69,7 @@ __global__ void k_enc_cdf(fgmm::QCfg q, int64_t n, const int32_t* __restrict__ s
     cf[i] = enc_cdf_elem<K, kKind, kFast, true>(q, n_total, gather_index(idx, i, n_total), sym,
                                                  w, mu, sg, status);
   else
-    cf[i] = enc_cdf_elem<K, kKind, kFast, true>(q, n, i, sym, w, mu, sg, status);
+    cf[i] = enc_cdf_elem<K, kKind, kFast, true, kBuf>(q, n, i, sym, w, mu, sg, status);
 }
 
 // Decode with L lanes per stream (L = 1: one lane per stream and a binary

@@ -32,6 +32,15 @@ __host__ __device__ inline bool buffer_offsets_fit(int K, int64_t n, int64_t S,
   return n >= 0 && S >= 1 && 4 * ((int64_t)K * n + 4 * S) <= lim && 2 * (total_words + 1) <= lim;
 }
 
+// The same for the encode's buffer path: the K planes, and the (c, f) words
+// of positions down to a block (8 steps) before a stream's first element,
+// whose offsets wrap below 0 to values past the words (read as 0: those
+// steps are not live).
+__host__ __device__ inline bool encode_offsets_fit(int K, int64_t n, int64_t S) {
+  const int64_t lim = 0xFFFFFFFFll;
+  return n >= 0 && S >= 1 && 4 * ((int64_t)K * n) <= lim && 4 * (n + 8 * S) <= lim;
+}
+
 // Element of a subset pass, clamped into the latent so that an invalid
 // index (reported as EINVAL by the pass's index check) never reads or
 // writes outside the buffers.
@@ -216,15 +225,36 @@ __device__ __forceinline__ int32_t search_group(const Elem<K>& e, const QCfg& q,
 // 16 bits: c_j < M <= 2^16 for j < N, f_j <= M - N + 1 < 2^16). A symbol
 // outside [lo, hi] sets kStRange in *status, or with kSentinel gives the
 // word 0 (f = 0, which no valid symbol has), which the rANS pass reports.
-template <int K, int kKind, bool kFast, bool kSentinel = false>
+// With kBuf the symbol and the parameters are read through buffer resources
+// (one 32-bit offset, plane rows at scalar offsets k n 4; the caller checks
+// encode_offsets_fit).
+template <int K, int kKind, bool kFast, bool kSentinel = false, bool kBuf = false>
 __device__ __forceinline__ uint32_t enc_cdf_elem(const QCfg& q, int64_t n, int64_t i,
                                                  const int32_t* __restrict__ sym,
                                                  const float* __restrict__ w,
                                                  const float* __restrict__ mu,
                                                  const float* __restrict__ sg, uint32_t* status) {
   float rw[K], rm[K], rs[K];
-  load_raw<K>(w, mu, sg, n, i, rw, rm, rs);
-  int32_t j = sym[i] - q.lo;
+  int32_t j;
+  if constexpr (kBuf) {
+    const int nb = (int)(uint32_t)(K * n * 4);
+    const __amdgpu_buffer_rsrc_t bw_ = __builtin_amdgcn_make_buffer_rsrc((void*)w, (short)0, nb, kRsrcWord3);
+    const __amdgpu_buffer_rsrc_t bm_ = __builtin_amdgcn_make_buffer_rsrc((void*)mu, (short)0, nb, kRsrcWord3);
+    const __amdgpu_buffer_rsrc_t bsg_ = __builtin_amdgcn_make_buffer_rsrc((void*)sg, (short)0, nb, kRsrcWord3);
+    const __amdgpu_buffer_rsrc_t bsy_ = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)sym, (short)0, (int)(uint32_t)(n * 4), kRsrcWord3);
+    const uint32_t o = (uint32_t)i * 4u, plane = (uint32_t)(n * 4);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      rw[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(bw_, o, k * plane, 0));
+      rm[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(bm_, o, k * plane, 0));
+      rs[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(bsg_, o, k * plane, 0));
+    }
+    j = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(bsy_, o, 0, 0) - q.lo;
+  } else {
+    load_raw<K>(w, mu, sg, n, i, rw, rm, rs);
+    j = sym[i] - q.lo;
+  }
   const bool out = j < 0 || j >= q.N;
   if (out) {
     if (!kSentinel) atomicOr(status, kStRange);
@@ -348,6 +378,7 @@ __device__ __forceinline__ uint32_t rans_stream(int64_t n, int64_t S, int P, int
 // per block is for those loads only. Returns the final state; *count
 // receives the number of words (at most n_s), *zero_f whether a word had
 // f = 0.
+template <bool kBuf = false>
 __device__ __forceinline__ uint32_t rans_stream_lds(int64_t n, int64_t S, int P, int64_t s,
                                                     const uint32_t* __restrict__ cf,
                                                     uint16_t* col, int stride, int trash_row,
@@ -362,8 +393,23 @@ __device__ __forceinline__ uint32_t rans_stream_lds(int64_t n, int64_t S, int P,
   for (int d = 0; d < kDepth; ++d) dS[d] = (int64_t)d * S;
   uint32_t buf[kDepth];
   int64_t base = s + (ns - 1) * S;  // position ns - 1
+  // kBuf: the words through a buffer resource, offsets in bytes; a position
+  // below 0 wraps to an offset past the words (encode_offsets_fit), which
+  // reads 0 (such steps are not live)
+  [[maybe_unused]] __amdgpu_buffer_rsrc_t bcf_;
+  [[maybe_unused]] uint32_t ob = 0;
+  const uint32_t dS4 = (uint32_t)S * 4u;
+  if constexpr (kBuf) {
+    bcf_ = __builtin_amdgcn_make_buffer_rsrc((void*)cf, (short)0, (int)(uint32_t)(n * 4),
+                                             kRsrcWord3);
+    ob = (uint32_t)base * 4u;
 #pragma unroll
-  for (int d = 0; d < kDepth; ++d) buf[d] = (ns - 1 - d >= 0) ? cf[base - dS[d]] : 0u;
+    for (int d = 0; d < kDepth; ++d)
+      buf[d] = __builtin_amdgcn_raw_buffer_load_b32(bcf_, ob - (uint32_t)d * dS4, 0, 0);
+  } else {
+#pragma unroll
+    for (int d = 0; d < kDepth; ++d) buf[d] = (ns - 1 - d >= 0) ? cf[base - dS[d]] : 0u;
+  }
   const int64_t step = (int64_t)kDepth * S;
   bool zf = false;
   for (int64_t p = ns - 1; p >= 0; p -= kDepth) {
@@ -372,11 +418,18 @@ __device__ __forceinline__ uint32_t rans_stream_lds(int64_t n, int64_t S, int P,
     uint32_t cur[kDepth];
 #pragma unroll
     for (int d = 0; d < kDepth; ++d) cur[d] = buf[d];
+    if constexpr (kBuf) {
+      ob -= (uint32_t)kDepth * dS4;
 #pragma unroll
-    for (int d = 0; d < kDepth; ++d) {
-      // unconditional (positions below 0 reload position 0)
-      const int64_t at = base - dS[d];
-      buf[d] = cf[at >= s ? at : s];
+      for (int d = 0; d < kDepth; ++d)
+        buf[d] = __builtin_amdgcn_raw_buffer_load_b32(bcf_, ob - (uint32_t)d * dS4, 0, 0);
+    } else {
+#pragma unroll
+      for (int d = 0; d < kDepth; ++d) {
+        // unconditional (positions below 0 reload position 0)
+        const int64_t at = base - dS[d];
+        buf[d] = cf[at >= s ? at : s];
+      }
     }
 #pragma unroll
     for (int d = 0; d < kDepth; ++d) {
