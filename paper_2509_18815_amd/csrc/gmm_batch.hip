@@ -74,7 +74,9 @@ __global__ void kb_reset(uint32_t* p, int64_t count) {
   if (i < count) p[i] = 0u;
 }
 
-template <int K, int kKind, bool kFast>
+// kBuf: every latent's offsets fit enc_cdf_elem's buffer path
+// (encode_offsets_fit).
+template <int K, int kKind, bool kFast, bool kBuf = false>
 __global__ void __launch_bounds__(kCdfBlock)
     kb_enc_cdf(const LatentDesc* __restrict__ desc, QCfg q, const int32_t* __restrict__ blk_latent,
                uint32_t* __restrict__ cf, uint32_t* status) {
@@ -82,8 +84,8 @@ __global__ void __launch_bounds__(kCdfBlock)
   const LatentDesc& d = desc[b];
   const int64_t i = ((int64_t)blockIdx.x - d.cdf_blk0) * kCdfBlock + threadIdx.x;
   if (i >= d.n) return;
-  cf[d.elem_base + i] = enc_cdf_elem<K, kKind, kFast>(q, d.n, i, d.sym, d.w, d.mu, d.sg,
-                                                      &status[b]);
+  cf[d.elem_base + i] = enc_cdf_elem<K, kKind, kFast, false, kBuf>(q, d.n, i, d.sym, d.w, d.mu,
+                                                                   d.sg, &status[b]);
 }
 
 // Work item = one rANS block (256 streams of one latent).
@@ -177,7 +179,7 @@ __global__ void __launch_bounds__(kPBlock)
 // writes offsets[S] and flags ENOSPC. Dynamic LDS: words[cap][256] for the
 // largest cap of the plan. Schedules: flat (one item per workgroup, taken
 // by ticket) and dynamic.
-template <int SPL>
+template <int SPL, bool kBuf = false>
 __global__ void __launch_bounds__(kRBlock / SPL)
     kb_enc_rans_lds(const LatentDesc* __restrict__ desc, int P, int trash_row,
                     const int32_t* __restrict__ items,
@@ -191,7 +193,9 @@ __global__ void __launch_bounds__(kRBlock / SPL)
   for (;;) {
     if (threadIdx.x == 0) item_sh = (int64_t)atomicAdd(queue, 1u);
     __syncthreads();
-    const int64_t item = item_sh;
+    // wavefront-uniform in a scalar register: the latent's descriptor and
+    // the buffer resource built from it stay scalar
+    const int64_t item = (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)item_sh);
     if (item >= n_items) break;
     const int64_t blk = items[item];
     const int b = blk_latent[blk];
@@ -203,8 +207,8 @@ __global__ void __launch_bounds__(kRBlock / SPL)
     bool zf = false;
     if (SPL == 1) {
       if (sa < d.S)
-        xa = rans_stream_lds(d.n, d.S, P, sa, lcf, words + threadIdx.x, kRBlock, trash_row, &ca,
-                             &zf);
+        xa = rans_stream_lds<kBuf>(d.n, d.S, P, sa, lcf, words + threadIdx.x, kRBlock, trash_row,
+                                   &ca, &zf);
     } else if (sa < d.S) {
       // a lane whose second stream lies past S steps its first one twice;
       // the copy's words go to an unused column and are dropped
@@ -499,12 +503,21 @@ int enqueue(gmm_plan* p, const Config& c, hipStream_t st) {
   uint32_t* queue = p->d_bits + B;
   const int64_t persist_grid = (int64_t)p->num_cus * c.waves_per_cu;
   if (p->op == 0) {
+    // buffer resources when every latent's offsets fit 32 bits
+    bool ebuf = true;
+    for (int b = 0; b < B; ++b) ebuf = ebuf && encode_offsets_fit(p->cfg.K, p->n[b], p->S[b]);
     if (p->n_cdf_blk > 0) {
       dispatch(p->cfg.K, p->cfg.cdf_kind, p->fast, [&](auto Kc, auto kc, auto fc) {
-        hipLaunchKernelGGL((kb_enc_cdf<decltype(Kc)::value, decltype(kc)::value,
-                                       decltype(fc)::value>),
-                           dim3((unsigned)p->n_cdf_blk), dim3(kCdfBlock), 0, st, p->d_desc, p->q,
-                           p->d_cdf_blk, p->d_cf, p->d_bits);
+        constexpr int K_ = decltype(Kc)::value, KI = decltype(kc)::value;
+        constexpr bool F = decltype(fc)::value;
+        if (ebuf)
+          hipLaunchKernelGGL((kb_enc_cdf<K_, KI, F, true>), dim3((unsigned)p->n_cdf_blk),
+                             dim3(kCdfBlock), 0, st, p->d_desc, p->q, p->d_cdf_blk, p->d_cf,
+                             p->d_bits);
+        else
+          hipLaunchKernelGGL((kb_enc_cdf<K_, KI, F>), dim3((unsigned)p->n_cdf_blk),
+                             dim3(kCdfBlock), 0, st, p->d_desc, p->q, p->d_cdf_blk, p->d_cf,
+                             p->d_bits);
       });
     }
     if (c.lds) {
@@ -520,6 +533,11 @@ int enqueue(gmm_plan* p, const Config& c, hipStream_t st) {
                            p->d_desc, p->cfg.precision, (int)p->cap_max, p->d_rans_items,
                            p->n_rans_blk, c.sched,
                            queue, p->d_rans_blk, p->d_cf, p->d_slots, p->d_bits);
+      else if (ebuf)
+        hipLaunchKernelGGL((kb_enc_rans_lds<1, true>), dim3((unsigned)grid), dim3(kRBlock), lds,
+                           st, p->d_desc, p->cfg.precision, (int)p->cap_max, p->d_rans_items,
+                           p->n_rans_blk, c.sched, queue, p->d_rans_blk, p->d_cf, p->d_slots,
+                           p->d_bits);
       else
         hipLaunchKernelGGL(kb_enc_rans_lds<1>, dim3((unsigned)grid), dim3(kRBlock), lds, st,
                            p->d_desc, p->cfg.precision, (int)p->cap_max, p->d_rans_items,
@@ -607,6 +625,9 @@ bool lds_ready() {
                           hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)kRansLdsMax) == hipSuccess &&
       hipFuncSetAttribute((const void*)kb_enc_rans_lds<2>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)kRansLdsMax) == hipSuccess &&
+      hipFuncSetAttribute((const void*)kb_enc_rans_lds<1, true>,
                           hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)kRansLdsMax) == hipSuccess;
   return ok;
