@@ -664,8 +664,8 @@ def bracket_few_streams_form(api, synth, dev, name, model, reps=10):
     """A latent with few streams (the 320x48x32 latent at 4,096 streams, or
     the 192x16x16 latent at 256 streams) decoded by lane groups: the plain
     (L+1)-ary search at the library's automatic L (8 and 16 lanes per stream
-    here) against the group form of the learned bracket (16 lanes, one
-    16-boundary round around the prediction), same bitstream."""
+    here) against the group form of the learned bracket at the same L (one
+    round of L boundaries around the prediction), same bitstream."""
     import torch
     cfgd = synth.CONFIGS[name]
     lat = synth.make_latents(cfgd, backend="torch", device=dev)[0]
@@ -691,7 +691,8 @@ def bracket_few_streams_form(api, synth, dev, name, model, reps=10):
     assert torch.equal(dec, lat.symbols) and L.st.tolist() == [0, 0]
     br.close()
     return {"shape": list(lat.shape), "n": L.n, "streams": L.S,
-            "plain_lanes_per_stream": api.decode_lanes(L.cfg), "bracket_lanes_per_stream": 16,
+            "plain_lanes_per_stream": api.decode_lanes(L.cfg),
+            "bracket_lanes_per_stream": api.decode_lanes(L.cfg),
             "plain_decode_sym_s": L.n / t_plain, "bracket_decode_sym_s": L.n / t_br,
             "plain_decode_ms": round(t_plain * 1e3, 4), "bracket_decode_ms": round(t_br * 1e3, 4),
             "gain": t_plain / t_br, "hit_rate": hits / max(hits + misses, 1),

@@ -369,12 +369,13 @@ int gmm_plan_destroy(gmm_plan* plan);
  * sequential rounds to ceil(log_{lanes+1} N) at the cost of more total
  * evaluations (for latents with few streams); 0 (default) chooses from the
  * stream count: the smallest power of two up to 32 that gives at least
- * 65,536 lanes, which (without a bracket) is then halved, down to 2, while
- * the (lanes+1)-ary search needs no more rounds. With a bracket, 16 or more lanes select the group form
- * with 16 lanes per stream (the network's prediction seeds one round that
- * evaluates 16 consecutive boundaries, with a 17-ary search as fallback),
- * 8 lanes the group form with 8 (8 boundaries, 9-ary fallback), fewer the
- * one-lane form (a verified bracket of radius R, then a binary search).
+ * 65,536 lanes, which is then halved, down to 2, while the (lanes+1)-ary
+ * search needs no more rounds. With a bracket, 16 or more lanes select the
+ * group form with 16 lanes per stream (the network's prediction seeds one
+ * round that evaluates 16 consecutive boundaries, with a 17-ary search as
+ * fallback), 8 lanes the group form with 8 (8 boundaries, 9-ary fallback),
+ * fewer the one-lane form (a verified bracket of radius R, then a binary
+ * search).
  * Output is identical for every choice. GMM_EINVAL otherwise. */
 int gmm_set_decode_lanes(int32_t lanes);
 

@@ -70,7 +70,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
 }
 
 // Group form: LG = 16 or 8 lanes per stream, 64 / LG streams per wavefront.
-template <int K, int kKind, bool kFast, int LG>
+template <int K, int kKind, bool kFast, int LG, bool kBuf = false>
 __global__ void __launch_bounds__(256)
     k_decode_bracket_group(QCfg q, int P, int64_t n, int64_t S, const uint16_t* __restrict__ bs,
                            int64_t total_words, const int64_t* __restrict__ offsets,
@@ -84,8 +84,8 @@ __global__ void __launch_bounds__(256)
     GroupModel gm;
     load_group_model(br, gm);
     unsigned long long cnt[4] = {0, 0, 0, 0};
-    bracket_group_decode<K, kKind, kFast, LG>(q, P, n, S, s0, bs, total_words, offsets, w, mu,
-                                              sg, sym, status, br, gm, cnt);
+    bracket_group_decode<K, kKind, kFast, LG, kBuf>(q, P, n, S, s0, bs, total_words, offsets, w,
+                                                    mu, sg, sym, status, br, gm, cnt);
     bracket_flush_stats(cnt, stats);
   }
   grid_finish_status(status, dev_status);
@@ -131,22 +131,30 @@ int decode_bracket_launch(const gmm_cfg* cfg, int64_t n, const uint16_t* bs, int
   const int64_t S = cfg->num_streams;
   const QCfg q = make_qcfg(cfg);
   hipLaunchKernelGGL(k_fill_u32_bracket, dim3(1), dim3(64), 0, st, status);
-  const int L = (lanes > 0) ? lanes : default_lanes_per_stream(S);
+  // the plain decode's choice (4,096 streams, N = 511: the 8-lane group
+  // form, 124.8-126.3 us on the 320x48x32 latent against 132.9-133.1 us
+  // for 16 lanes and 130.1-130.5 us for the plain 8-lane search)
+  const int L = plain_decode_lanes(cfg, lanes);
+  const bool buf = buffer_offsets_fit(cfg->K, n, S, total_words);
   dispatch(cfg->K, cfg->cdf_kind, fast, [&](auto Kc, auto kc, auto fc) {
     constexpr int K_ = decltype(Kc)::value;
     if constexpr (K_ <= 5) {
-      if (L >= 16)
-        hipLaunchKernelGGL((k_decode_bracket_group<K_, decltype(kc)::value, decltype(fc)::value,
-                                                   16>),
-                           dim3((unsigned)((S + 15) / 16)), dim3(256), 0, st, q, cfg->precision,
-                           n, S, bs, total_words, offsets, w, mu, sg, symbols, status, br->dev,
-                           (unsigned long long*)stats, dev_status);
+      constexpr int KI = decltype(kc)::value;
+      constexpr bool F = decltype(fc)::value;
+#define FG_GRP(LG, BUF)                                                                      \
+  hipLaunchKernelGGL((k_decode_bracket_group<K_, KI, F, LG, BUF>),                          \
+                     dim3((unsigned)((S + 256 / LG - 1) / (256 / LG))), dim3(256),           \
+                     0, st, q, cfg->precision, n, S, bs, total_words, offsets, w, mu, sg,    \
+                     symbols, status, br->dev, (unsigned long long*)stats, dev_status)
+      if (L >= 16 && buf)
+        FG_GRP(16, true);
+      else if (L >= 16)
+        FG_GRP(16, false);
+      else if (L == 8 && buf)
+        FG_GRP(8, true);
       else if (L == 8)
-        hipLaunchKernelGGL((k_decode_bracket_group<K_, decltype(kc)::value, decltype(fc)::value,
-                                                   8>),
-                           dim3((unsigned)((S + 31) / 32)), dim3(256), 0, st, q, cfg->precision,
-                           n, S, bs, total_words, offsets, w, mu, sg, symbols, status, br->dev,
-                           (unsigned long long*)stats, dev_status);
+        FG_GRP(8, false);
+#undef FG_GRP
       else
         hipLaunchKernelGGL((k_decode_bracket<K_, decltype(kc)::value, decltype(fc)::value>),
                            dim3((unsigned)((S + 63) / 64)), dim3(64), 0, st, q, cfg->precision,

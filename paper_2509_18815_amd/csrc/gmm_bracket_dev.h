@@ -494,8 +494,11 @@ __device__ __forceinline__ float mlp_group(const BracketDev* __restrict__ br, co
 // and store nothing): the matrix-core inference needs all 64 lanes.
 // Counters (lane 0 of each group): hit / miss symbols; lane 0 of the
 // wavefront also counts wavefront steps and steps on which every active
-// stream hit.
-template <int K, int kKind, bool kFast, int LG>
+// stream hit. kBuf: parameters, refill words and symbols through buffer
+// resources with 32-bit offsets, as decode_stream's buffer path (the caller
+// checks buffer_offsets_fit; loads are then unconditional, the resources'
+// range checks covering groups past S).
+template <int K, int kKind, bool kFast, int LG, bool kBuf = false>
 __device__ __forceinline__ void bracket_group_decode(
     const QCfg& q, int P, int64_t n, int64_t S, int64_t s0, const uint16_t* __restrict__ bs,
     int64_t total_words, const int64_t* __restrict__ offsets, const float* __restrict__ w,
@@ -532,16 +535,46 @@ __device__ __forceinline__ void bracket_group_decode(
   // load is unconditional, positions past the end reload the last element
   constexpr int kRing = 2;
   float rw[kRing][K], rm[kRing][K], rs[kRing][K];
+  [[maybe_unused]] __amdgpu_buffer_rsrc_t bw_, bm_, bsg_, bbs_, bsym_;
+  [[maybe_unused]] uint32_t off_next = 0, off_last = 0, off_cur = 0, plane = 0;
+  if constexpr (kBuf) {
+    const int nb = (int)(uint32_t)(K * n * 4);
+    bw_ = __builtin_amdgcn_make_buffer_rsrc((void*)w, (short)0, nb, kRsrcWord3);
+    bm_ = __builtin_amdgcn_make_buffer_rsrc((void*)mu, (short)0, nb, kRsrcWord3);
+    bsg_ = __builtin_amdgcn_make_buffer_rsrc((void*)sg, (short)0, nb, kRsrcWord3);
+    bbs_ = __builtin_amdgcn_make_buffer_rsrc((void*)bs, (short)0,
+                                             (int)(uint32_t)(total_words * 2), kRsrcWord3);
+    bsym_ = __builtin_amdgcn_make_buffer_rsrc((void*)sym, (short)0, (int)(uint32_t)(n * 4),
+                                              kRsrcWord3);
+    plane = (uint32_t)(n * 4);
+    off_cur = (uint32_t)s * 4u;
+    off_last = (uint32_t)(s + last * S) * 4u;
+    off_next = off_cur;
+  }
 #pragma unroll
   for (int d = 0; d < kRing; ++d) {
-    const int64_t pp = (d < last) ? d : last;
+    if constexpr (kBuf) {
+      const uint32_t o = off_next < off_last ? off_next : off_last;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      rw[d][k] = 0.0f;
-      rm[d][k] = 0.0f;
-      rs[d][k] = 1.0f;
+      for (int k = 0; k < K; ++k) {
+        rw[d][k] = __builtin_bit_cast(
+            float, __builtin_amdgcn_raw_buffer_load_b32(bw_, o, k * plane, 0));
+        rm[d][k] = __builtin_bit_cast(
+            float, __builtin_amdgcn_raw_buffer_load_b32(bm_, o, k * plane, 0));
+        rs[d][k] = __builtin_bit_cast(
+            float, __builtin_amdgcn_raw_buffer_load_b32(bsg_, o, k * plane, 0));
+      }
+      off_next += (uint32_t)S * 4u;
+    } else {
+      const int64_t pp = (d < last) ? d : last;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        rw[d][k] = 0.0f;
+        rm[d][k] = 0.0f;
+        rs[d][k] = 1.0f;
+      }
+      if (seg_ok && ns > 0) load_raw<K>(w, mu, sg, n, s + pp * S, rw[d], rm[d], rs[d]);
     }
-    if (seg_ok && ns > 0) load_raw<K>(w, mu, sg, n, s + pp * S, rw[d], rm[d], rs[d]);
   }
   for (int64_t p0 = 0; p0 < ns_max; p0 += kRing) {
 #pragma unroll
@@ -552,9 +585,15 @@ __device__ __forceinline__ void bracket_group_decode(
       float cw[K], cm[K], cs[K];
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        cw[k] = opaque_copy(rw[d][k]);
-        cm[k] = opaque_copy(rm[d][k]);
-        cs[k] = opaque_copy(rs[d][k]);
+        if constexpr (kBuf) {
+          cw[k] = rw[d][k];
+          cm[k] = rm[d][k];
+          cs[k] = rs[d][k];
+        } else {
+          cw[k] = opaque_copy(rw[d][k]);
+          cm[k] = opaque_copy(rm[d][k]);
+          cs[k] = opaque_copy(rs[d][k]);
+        }
       }
       const Elem<K> e = make_elem<K, kFast, kKind>(q, cw, cm, cs);
       const uint32_t slot = x & mask;
@@ -608,7 +647,13 @@ __device__ __forceinline__ void bracket_group_decode(
         ++cnt[3];
         if (lead_hit == lead) ++cnt[2];
       }
-      if (act && g == 0) sym[s + p * S] = q.lo + lo;
+      if constexpr (kBuf) {
+        if (act && g == 0)
+          __builtin_amdgcn_raw_buffer_store_b32((uint32_t)(q.lo + lo), bsym_, off_cur, 0, 0);
+        off_cur += (uint32_t)S * 4u;
+      } else {
+        if (act && g == 0) sym[s + p * S] = q.lo + lo;
+      }
       // state update and refill as selects (all lanes of a group agree)
       const uint32_t xs = (c_hi - c_lo) * (x >> P) + slot - c_lo;
       const bool refill = act && xs < (1u << 16);
@@ -617,10 +662,28 @@ __device__ __forceinline__ void bracket_group_decode(
       x = act ? xr : x;
       bad = bad || (refill && !have);
       ptr += (refill && have) ? 1 : 0;
-      nword = seg_ok ? bs[ptr < b ? ptr : bl] : 0u;
-      asm volatile("" ::: "memory");  // keep the word's load ahead of the ring's
-      const int64_t pn = p + kRing;
-      if (seg_ok) load_raw<K>(w, mu, sg, n, s + (pn < last ? pn : last) * S, rw[d], rm[d], rs[d]);
+      if constexpr (kBuf) {
+        // ptr <= b <= total_words (a word past the bitstream reads 0)
+        nword = __builtin_amdgcn_raw_buffer_load_b16(bbs_, (uint32_t)ptr * 2u, 0, 0);
+        asm volatile("" ::: "memory");  // keep the word's load ahead of the ring's
+        const uint32_t o = off_next < off_last ? off_next : off_last;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          rw[d][k] = __builtin_bit_cast(
+              float, __builtin_amdgcn_raw_buffer_load_b32(bw_, o, k * plane, 0));
+          rm[d][k] = __builtin_bit_cast(
+              float, __builtin_amdgcn_raw_buffer_load_b32(bm_, o, k * plane, 0));
+          rs[d][k] = __builtin_bit_cast(
+              float, __builtin_amdgcn_raw_buffer_load_b32(bsg_, o, k * plane, 0));
+        }
+        off_next += (uint32_t)S * 4u;
+      } else {
+        nword = seg_ok ? bs[ptr < b ? ptr : bl] : 0u;
+        asm volatile("" ::: "memory");  // keep the word's load ahead of the ring's
+        const int64_t pn = p + kRing;
+        if (seg_ok)
+          load_raw<K>(w, mu, sg, n, s + (pn < last ? pn : last) * S, rw[d], rm[d], rs[d]);
+      }
     }
   }
   if (seg_ok && (x != (1u << 16) || ptr != b)) bad = true;

@@ -32,6 +32,10 @@ int decode_launch(const gmm_cfg* cfg, int64_t n, const uint16_t* bs, int64_t tot
                   int32_t* dev_status = nullptr);
 int search_rounds_lps(int32_t N, int L);
 int default_lanes_per_stream(int64_t S);
+// Lanes per stream of a decode of cfg (lanes > 0: the caller's choice; else
+// the automatic one: default_lanes_per_stream halved while the search needs
+// no more rounds).
+int plain_decode_lanes(const gmm_cfg* cfg, int lanes);
 int decode_bracket_launch(const gmm_cfg* cfg, int64_t n, const uint16_t* bs, int64_t total_words,
                           const int64_t* offsets, const float* w, const float* mu,
                           const float* sg, int32_t* symbols, const gmm_bracket* bracket,

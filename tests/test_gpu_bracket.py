@@ -246,12 +246,13 @@ def test_bracket_decode_matches_oracle_on_corruption(api, orc, trained, lanes):
     br.close()
 
 
-@pytest.mark.parametrize("lanes", [0, 8], indirect=True)
+@pytest.mark.parametrize("lanes", [0, 8, 16], indirect=True)
 def test_group_bracket_decode_kodak_latent(api, orc, trained, lanes):
     """The 320x48x32 latent at 4,096 streams with a bracket decodes by lane
-    groups (16 lanes per stream by default, or 8): the group form of the
-    bracket (matrix-core inference for four streams
-    per wavefront, one 16-boundary window round) is bit-identical to the
+    groups (8 lanes per stream by default, as the plain decode, or 16): the
+    group form of the bracket (matrix-core inference for eight or four
+    streams per wavefront, one window round of 8 or 16 boundaries) is
+    bit-identical to the
     plain decode; a trained model hits on nearly every symbol (which also
     checks the 16x16x32 operand layout: a wrong layout predicts noise); an
     untrained one misses and takes the fallback search everywhere."""
@@ -269,7 +270,9 @@ def test_group_bracket_decode_kodak_latent(api, orc, trained, lanes):
     assert torch.equal(dec, lat.symbols)
     hits, misses, all_hit, steps = stats.cpu().tolist()
     assert hits + misses == lat.n
-    assert hits / lat.n > (0.97 if lanes != 8 else 0.93), hits / lat.n
+    window = lanes or api.decode_lanes(cfg)  # boundaries per window round
+    assert window in (8, 16)
+    assert hits / lat.n > (0.97 if window == 16 else 0.93), hits / lat.n
     rng = np.random.default_rng(19)
     bad = api.Bracket(3, rand_net(rng, 10, orc, 1.0), trained.in_mean, trained.in_std, 0.0, 50.0)
     stats.zero_()
