@@ -15,7 +15,7 @@ step: (n_kodak + n_4k) * steps / elapsed. It is measured first in the
 process; after the other forms the same warm-up and timed steps run again
 (`repeat_after_forms`), when the GPU's clocks have settled under load.
 
-Prints one JSON line (rank 0 only; this build runs on one GPU).
+Prints one JSON line (rank 0 only; the benchmark runs on one GPU).
 """
 from __future__ import annotations
 
@@ -227,7 +227,7 @@ def cpu_baseline_legs(dev) -> dict:
 
 def peak_probes(api, dev) -> dict:
     """Measured ceilings of this GPU beside the published peaks: the issue
-    rate of independent binary32 fmas in this build's (non-packed) form, and
+    rate of independent binary32 fmas in the library's (non-packed) form, and
     a 1 GiB device copy (bytes read + written per second)."""
     import torch
     stream = torch.cuda.current_stream()
@@ -909,8 +909,8 @@ def main():
     ap.add_argument("--no-peak-probes", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
-              "multi-GPU sharding is described in DESIGN.md but not run.", file=sys.stderr)
+        print(f"bench.py: measures one GPU only (asked for --gpus {args.gpus}); "
+              "the sharded multi-GPU path is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -1026,7 +1026,7 @@ def main():
             # bytes against 8 TB/s, and VALU lane-instructions (64 per
             # wavefront instruction) against the issue rate of non-packed
             # FP32 instructions, 256 CU x 4 SIMD x 16 lanes x 2.4 GHz (packed
-            # FP32 is not generated by this build; the 157.3 TFLOP/s peak
+            # FP32 is disabled in the library's compile flags; the 157.3 TFLOP/s peak
             # counts packed FMA as 4 flops per lane)
             counters = {"source": os.path.relpath(TRAFFIC_FILE, ROOT),
                         "hbm_GBps": round(traffic / dec_t / 1e9, 1),

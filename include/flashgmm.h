@@ -413,7 +413,7 @@ int gmm_params_from_raw(int32_t K, int64_t n, const float* logits, const float* 
 /* ---- Peak probes (diagnostics; not part of the coder) ----
  * gmm_fma_probe: `threads` lanes (a multiple of 256) each run 8 independent
  * chains of `iters` binary32 fused multiply-adds (one fma per lane per
- * instruction, as this build compiles them) and store a sum to out [device,
+ * instruction, as the library is compiled) and store a sum to out [device,
  * float32 [threads]]; lane-fmas = threads * iters * 8. gmm_copy_probe:
  * copies `bytes` (a multiple of 16) from src to dst [device]. Both are
  * asynchronous on stream; the caller times them. GMM_EINVAL on bad sizes. */

@@ -1,5 +1,5 @@
 // Peak probes (diagnostics beside the coder): the issue rate of independent
-// binary32 fused multiply-adds in this build's instruction forms (packed
+// binary32 fused multiply-adds in the library's instruction forms (packed
 // FP32 is disabled at compile time, so one fma per lane per instruction)
 // and a plain device copy. The benchmark times them with HIP events to set
 // the coder kernels' rates beside what the GPU sustains.

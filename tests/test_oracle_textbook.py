@@ -16,9 +16,8 @@ evaluated here independently in binary64 with no rearrangement:
 (A&S 26.2.17 with the handbook's p and b1..b5), the mixture of Eq. (2),
 F(b) = sum_k w_k Phi((b - mu_k) / sigma_k), at every half-integer boundary
 b = lo + j - 1/2 of Eq. (1), and its quantization c_j = j + floor(F (M-N))
-(the quantization rule this build reads into the paper's "quantized values
-of CDF"). Both sides use the same approximation, so what separates them is
-the binary32 evaluation alone; the allowance below is the 2^-22 float
+(the oracle's reading of the paper's quantized CDF). Both sides use the
+same approximation, so what separates them is the binary32 evaluation alone; the allowance below is the 2^-22 float
 evaluation budget plus the A&S bound 7.5e-8 (the paper's quoted error),
 and the quantized columns may differ by one count where floor(F (M-N))
 lands within that distance of an integer. The logistic kind is checked the
