@@ -287,7 +287,7 @@ __global__ void __launch_bounds__(64)
     const int64_t s = (int64_t)t.y + lane / L;
     const int g = lane % L;
     if (s < d.S) {
-      const bool bad = decode_stream<K, kKind, kFast, L, false, false, kBuf>(
+      const bool bad = decode_stream<K, kKind, kFast, L, false, L == 1, kBuf>(
           q, P, rounds, d.n, d.S, s, g, d.bs, d.words, d.offsets, d.w, d.mu, d.sg, d.dec);
       if (bad && g == 0) atomicOr(&status[t.x], kStCorrupt);
     }

@@ -307,6 +307,7 @@ template <int K>
 struct Elem {
   float w[K], mu[K], r[K], rn[K];
   float hw;
+  float sc[K];  // the clamped scale sigma' (the decoder's search bracket)
 };
 
 template <int K>
@@ -339,6 +340,7 @@ __device__ __forceinline__ Elem<K> make_elem(const QCfg& q, const float (&rw)[K]
     e.w[k] = (w[k] < 0x1p-60f) ? 0.0f : w[k];
     e.mu[k] = rm[k];
     e.rn[k] = e.r[k] * kInv9;
+    e.sc[k] = s;
   }
   float ws = e.w[0];
 #pragma unroll

@@ -70,61 +70,12 @@ __device__ __forceinline__ int free_rounds(int rounds, int32_t N) {
   return nfree;
 }
 
-// The same search with the round counts fixed at compile time: the rounds
-// are straight-line code (no loop counters or back-edges between them), and
-// the interval is carried as the float boundary b_lo = lo + lo_mh instead of
-// the integer lo. Every value below is an integer or a half-integer of
-// magnitude < 2^23 (|lo| <= 2^22, slot < M <= 2^16), so each float sum and
-// difference is exact: b = b_lo + 2^r is b_mid, and s1 - b = slot + 1 - mid.
-// For an integer k and y >= 0, k >= floor(y) exactly when y < k + 1, so
-// slot >= c_mid = mid + floor(y) is the float test y < s1 - b: the same
-// decision as the integer form, without converting y or mid per round.
-// c_lo and c_hi are rebuilt at the end from the y of the rounds that set lo
-// and hi (initial y: 0 for c_0 = 0, M - 2^kRounds for c = M at 2^kRounds);
-// above N the contract's c_j = M is y = M - mid, which fails the test.
-template <int K, int kKind, bool kFast, int kRounds, int kFree>
-__device__ __forceinline__ int32_t search_fixed(const Elem<K>& e, const QCfg& q, uint32_t slot,
-                                                uint32_t& c_lo, uint32_t& c_hi) {
-  const float s1 = (float)(slot + 1u) + q.lo_mh;
-  const float bN = (float)q.N + q.lo_mh;
-  const float bM = (float)q.M + q.lo_mh;
-  float bl = q.lo_mh;
-  float yl = 0.0f;
-  float yh = (float)(q.M - (1u << kRounds));
-#pragma unroll
-  for (int i = 0; i < kRounds; ++i) {
-    const float b = bl + (float)(1 << (kRounds - 1 - i));
-    float y = cdf_scaled<K, kKind, kFast>(e, q, b);
-    if (i >= kFree) y = (b < bN) ? y : bM - b;
-    const bool right = y < s1 - b;
-    bl = right ? b : bl;
-    yl = right ? y : yl;
-    yh = right ? yh : y;
-  }
-  const int32_t lo = (int32_t)(bl - q.lo_mh);
-  c_lo = (uint32_t)lo + (uint32_t)yl;
-  c_hi = (uint32_t)(lo + 1) + (uint32_t)yh;
-  return lo;
-}
-
-// nfree = free_rounds(rounds, N), computed once by the caller. With
-// kStraight (A&S kind) the alphabets of 256, 511 and 1023 symbols take the
-// straight-line form (a wavefront-uniform branch on the kernel's
-// arguments). It pays where one wavefront per SIMD leaves the loop's scalar
-// and branch instructions exposed; it also holds more registers, so the
-// batched kernels, which rely on several wavefronts per SIMD, keep the loop.
-template <int K, int kKind, bool kFast, bool kStraight = false>
-__device__ __forceinline__ int32_t search_bs(const Elem<K>& e, const QCfg& q, int rounds,
-                                             int nfree, uint32_t slot, uint32_t& c_lo,
-                                             uint32_t& c_hi) {
-  if constexpr (kKind == 0 && kStraight) {
-    if (rounds == 9 && nfree == 8)
-      return search_fixed<K, kKind, kFast, 9, 8>(e, q, slot, c_lo, c_hi);
-    if (rounds == 8 && nfree == 8)
-      return search_fixed<K, kKind, kFast, 8, 8>(e, q, slot, c_lo, c_hi);
-    if (rounds == 10 && nfree == 9)
-      return search_fixed<K, kKind, kFast, 10, 9>(e, q, slot, c_lo, c_hi);
-  }
+// Exact binary search over [0, 2^rounds): the first nfree rounds probe
+// boundaries below N, the rest clamp c_j to M for j >= N.
+template <int K, int kKind, bool kFast>
+__device__ __forceinline__ int32_t search_loop(const Elem<K>& e, const QCfg& q, int rounds,
+                                               int nfree, uint32_t slot, uint32_t& c_lo,
+                                               uint32_t& c_hi) {
   int32_t lo = 0;
   c_lo = 0;
   c_hi = q.M;
@@ -148,6 +99,51 @@ __device__ __forceinline__ int32_t search_bs(const Elem<K>& e, const QCfg& q, in
   return lo;
 }
 
+// ---------------------------------------------------------------------
+// Bracketed search (one lane per stream, A&S kind). The decoder has to
+// find the j with c_j <= slot < c_{j+1}; since c_j is strictly increasing
+// that j is unique, and any procedure that proposes a candidate and then
+// confirms it with the exact c_j and c_{j+1} returns what the binary search
+// returns. The candidate comes from two steps that are not part of the
+// coding contract and may err (an error only costs time):
+//  1. a bracket from component quantiles: if every component has CDF value
+//     u at its own quantile mu_k + sigma_k z(u), the mixture's u-quantile
+//     lies between the smallest and the largest of them, so a rough z(u)
+//     (A&S 26.2.23, |error| < 4.5e-4) and the slot's position u give an
+//     index range [jl, jh] that usually holds j;
+//  2. a binary search over that range with an approximate Phi (A&S 26.2.17
+//     on the hardware reciprocal and exp2, no clamps): its comparisons
+//     differ from the exact ones only where the slot lies within about
+//     1e-6 (M - N) counts of a boundary.
+// Two exact evaluations then confirm the candidate; a lane whose candidate
+// fails runs the exact binary search (the looped form: it is rare, and one
+// copy keeps the unrolled decode loop small). The wavefront runs as many
+// approximate rounds as its widest bracket needs (at most the exact
+// search's), so it pays off when brackets are narrow: the components'
+// quantiles close together relative to their scales.
+constexpr float kQ23C0 = 2.515517f, kQ23C1 = 0.802853f, kQ23C2 = 0.010328f;
+constexpr float kQ23D1 = 1.432788f, kQ23D2 = 0.189269f, kQ23D3 = 0.001308f;
+constexpr float kAsP = 0.2316419f;
+constexpr float kInvSqrt2Pi = 0.3989422804014327f;
+constexpr float kNegHalfLog2e = -0.7213475204444817f;  // -log2(e) / 2
+constexpr float kNeg2Ln2 = -1.3862943611198906f;       // -2 ln 2
+// below 7 exact rounds (N <= 64) the plain search is as cheap; above 10
+// (N > 1024) the looped search serves
+constexpr int kBracketMinRounds = 7, kBracketMaxRounds = 10;
+
+// Approximate Phi(z) - 1/2 (error ~1e-7): the A&S 26.2.17 tail with the
+// hardware reciprocal and exp2.
+__device__ __forceinline__ float approx_half(float z) {
+  const float x = __builtin_fabsf(z);
+  const float t = __builtin_amdgcn_rcpf(fma32(x, kAsP, 1.0f));
+  float h = fma32(kAsB5 * kInvSqrt2Pi, t, kAsB4 * kInvSqrt2Pi);
+  h = fma32(h, t, kAsB3 * kInvSqrt2Pi);
+  h = fma32(h, t, kAsB2 * kInvSqrt2Pi);
+  h = fma32(h, t, kAsB1 * kInvSqrt2Pi);
+  const float g = __builtin_amdgcn_exp2f((z * z) * kNegHalfLog2e);
+  return __builtin_copysignf(fma32(-g, h * t, 0.5f), z);
+}
+
 // Maximum / minimum over the 16 lanes of a DPP row (every lane receives
 // it): rotations of the row by 1, 2, 4 and 8 lanes.
 __device__ __forceinline__ int32_t row16_max(int32_t v) {
@@ -163,6 +159,94 @@ __device__ __forceinline__ int32_t row16_min(int32_t v) {
   v = min(v, __builtin_amdgcn_mov_dpp(v, 0x124, 0xF, 0xF, true));
   v = min(v, __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, true));
   return v;
+}
+
+// The largest value over the wavefront's lanes of a small non-negative v
+// (lanes outside exec may contribute stale values: callers clamp).
+__device__ __forceinline__ int32_t wave_max_small(int32_t v) {
+  v = row16_max(v);
+  const int32_t a = max(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16));
+  const int32_t b = max(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48));
+  return max(a, b);
+}
+
+template <int K, bool kFast>
+__device__ __forceinline__ int32_t search_bracketed(const Elem<K>& e, const QCfg& q, int rounds,
+                                                    int nfree, uint32_t slot, uint32_t& c_lo,
+                                                    uint32_t& c_hi) {
+  const int32_t N = (int32_t)q.N;
+  // 1. bracket. The slot sits near j + F(b_j)(M - N) for the symbol j, so
+  // u = (slot + 1/2 - jbar) / (M - N), with jbar the index of the
+  // mixture's mean, approximates F at the symbol.
+  float wm = 0.0f;
+#pragma unroll
+  for (int k = 0; k < K; ++k) wm = fma32(e.w[k], e.mu[k], wm);
+  const float jbar = wm * (0.5f * __builtin_amdgcn_rcpf(e.hw)) - q.lo_mh;
+  const float u = ((float)slot + 0.5f - jbar) * __builtin_amdgcn_rcpf(q.span);
+  const float pu = __builtin_fmaxf(__builtin_fminf(u, 1.0f - u), 0x1p-30f);
+  const float t = __builtin_amdgcn_sqrtf(__builtin_amdgcn_logf(pu) * kNeg2Ln2);
+  const float num = fma32(fma32(kQ23C2, t, kQ23C1), t, kQ23C0);
+  const float den = fma32(fma32(fma32(kQ23D3, t, kQ23D2), t, kQ23D1), t, 1.0f);
+  const float xq = t - num * __builtin_amdgcn_rcpf(den);
+  const float z = (u < 0.5f) ? -xq : xq;
+  float qmin = fma32(e.sc[0], z, e.mu[0]), qmax = qmin;
+#pragma unroll
+  for (int k = 1; k < K; ++k) {
+    const float v = fma32(e.sc[k], z, e.mu[k]);
+    qmin = __builtin_fminf(qmin, v);
+    qmax = __builtin_fmaxf(qmax, v);
+  }
+  // symbol index of a value v: floor(v - (lo - 1/2)); one index of margin
+  const float fN1 = (float)(N - 1);
+  const int32_t jl = (int32_t)__builtin_fminf(
+      __builtin_fmaxf(__builtin_floorf(qmin - q.lo_mh) - 1.0f, 0.0f), fN1);
+  const int32_t jh = (int32_t)__builtin_fminf(
+      __builtin_fmaxf(__builtin_floorf(qmax - q.lo_mh) + 1.0f, (float)jl), fN1);
+  const int32_t wd = jh - jl;  // width - 1
+  const int32_t rl = (wd <= 0) ? 0 : 32 - __builtin_clz((uint32_t)wd);
+  const int32_t rw = min(wave_max_small(rl), rounds);
+  // 2. approximate binary search over [jl, jh]
+  float ws[K], zo[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    ws[k] = e.w[k] * q.span;
+    zo[k] = -e.mu[k] * e.r[k];
+  }
+  const float h0 = e.hw * q.span;
+  const float s1 = (float)(slot + 1u) + q.lo_mh;
+  int32_t j = jl;
+  for (int i = rw - 1; i >= 0; --i) {
+    const int32_t mid = j + (1 << i);
+    const float b = (float)min(mid, N - 1) + q.lo_mh;
+    float y = h0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) y = fma32(ws[k], approx_half(fma32(b, e.r[k], zo[k])), y);
+    j = (mid <= jh && y < s1 - b) ? mid : j;
+  }
+  // 3. confirm with the exact c_j and c_{j+1}
+  const uint32_t cl = cdf_at<K, 0, kFast>(e, q, j);
+  const uint32_t ch = cdf_at<K, 0, kFast>(e, q, j + 1);
+  if (cl <= slot && slot < ch) {
+    c_lo = cl;
+    c_hi = ch;
+    return j;
+  }
+  return search_loop<K, 0, kFast>(e, q, rounds, nfree, slot, c_lo, c_hi);
+}
+
+// nfree = free_rounds(rounds, N), computed once by the caller. With
+// kBracket (A&S kind, one lane per stream) alphabets of 65 to 1024 symbols
+// take the bracketed search (a wavefront-uniform branch on the kernel's
+// arguments); other kinds and sizes the exact loop.
+template <int K, int kKind, bool kFast, bool kBracket = false>
+__device__ __forceinline__ int32_t search_bs(const Elem<K>& e, const QCfg& q, int rounds,
+                                             int nfree, uint32_t slot, uint32_t& c_lo,
+                                             uint32_t& c_hi) {
+  if constexpr (kKind == 0 && kBracket) {
+    if (rounds >= kBracketMinRounds && rounds <= kBracketMaxRounds)
+      return search_bracketed<K, kFast>(e, q, rounds, nfree, slot, c_lo, c_hi);
+  }
+  return search_loop<K, kKind, kFast>(e, q, rounds, nfree, slot, c_lo, c_hi);
 }
 
 // (L+1)-ary search by a group of L lanes (lane g of the group, group mask
@@ -706,14 +790,14 @@ __device__ __forceinline__ float opaque_copy(float v) {
 // With kGather the coded sequence is the subset idx[0..n) of a latent of
 // n_total elements: pass position i reads its parameters at element idx[i]
 // of the [K][n_total] planes and writes its symbol to sym[idx[i]].
-// kStraight selects the straight-line binary search (search_bs).
+// kBracket selects the bracketed search for one lane per stream (search_bs).
 // With kBuf the parameters, the refill words and the symbols go through
 // buffer resources with 32-bit byte offsets: one offset per step for all
 // 3K parameter loads (the plane rows at constant scalar offsets k n 4), no
 // 64-bit address arithmetic, and no clamp for the refill word (a word past
 // the bitstream reads 0 by the resource's range check). The caller selects
 // it only when every offset fits: buffer_offsets_fit below.
-template <int K, int kKind, bool kFast, int L, bool kGather = false, bool kStraight = false,
+template <int K, int kKind, bool kFast, int L, bool kGather = false, bool kBracket = false,
           bool kBuf = false>
 __device__ __forceinline__ bool decode_stream(const QCfg& q, int P, int rounds, int64_t n,
                                               int64_t S, int64_t s, int g,
@@ -808,7 +892,7 @@ __device__ __forceinline__ bool decode_stream(const QCfg& q, int P, int rounds, 
         const Elem<K> e = make_elem<K, kFast, kKind>(q, cw, cm, cs);
         int32_t j;
         if (L == 1)
-          j = search_bs<K, kKind, kFast, kStraight>(e, q, rounds, nfree, slot, cl, ch);
+          j = search_bs<K, kKind, kFast, kBracket>(e, q, rounds, nfree, slot, cl, ch);
         else
           j = search_group<K, kKind, kFast, L>(e, q, rounds, slot, g, gbase, gmask, 0, q.N, cl,
                                                ch);

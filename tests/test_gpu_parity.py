@@ -129,7 +129,7 @@ def test_decode_lanes_per_stream_bit_exact(api, orc, lanes):
     rng = np.random.default_rng(lanes)
     try:
         # (6007, 96, 5, -511, 511, 0) at one lane per stream is the
-        # straight-line ten-round search of the A&S kind (N = 1023)
+        # bracketed search of the A&S kind (N = 1023)
         for n, S, K, lo, hi, kind in [(20011, 129, 3, -255, 255, 0), (5000, 64, 5, -511, 511, 1),
                                       (777, 1000, 2, -3, 3, 0), (40000, 300, 1, -128, 127, 0),
                                       (6007, 96, 5, -511, 511, 0)]:
@@ -153,12 +153,51 @@ def test_decode_lanes_per_stream_bit_exact(api, orc, lanes):
         api.set_decode_lanes(0)
 
 
+@pytest.mark.parametrize("lo,hi", [(-32, 32), (-32, 31), (-255, 255), (0, 1023), (-512, 512)])
+def test_bracketed_search_bit_exact(api, orc, lo, hi):
+    """One lane per stream, A&S kind: alphabets from 65 to 1024 symbols take
+    the bracketed search (candidate from component quantiles and an
+    approximate Phi, confirmed by two exact evaluations, exact search when
+    the candidate fails); 64 and 1025 symbols sit just outside it. Edge-of-
+    range parameters and symbols spread over the whole support (far tails,
+    where candidates fail most) decode to the oracle's symbols, and a
+    corrupted segment to the oracle's status and symbols."""
+    rng = np.random.default_rng(hi - lo)
+    n, S, K = 30011, 512, 5 if hi - lo > 600 else 3
+    w, mu, sig = synth.adversarial_params(rng, n, K)
+    half = n // 2
+    # half the symbols from the model's first component, half uniform
+    sym = np.empty(n, dtype=np.int32)
+    m0 = np.clip(mu[0, :half], lo - 2.0, hi + 2.0)
+    s0 = np.clip(sig[0, :half], 0.0, float(hi - lo))
+    sym[:half] = np.clip(np.rint(m0 + s0 * rng.normal(size=half)), lo, hi)
+    sym[half:] = rng.integers(lo, hi + 1, size=n - half)
+    ocfg = orc.make_cfg(K, lo, hi, 16, S, 0)
+    st, obs, ooff = orc.encode(ocfg, sym, w, mu, sig)
+    assert st == orc.OK
+    cfg = api.make_cfg(K, lo, hi, 16, S, 0)
+    api.set_decode_lanes(1)
+    try:
+        dec = torch.empty(n, dtype=torch.int32, device="cuda")
+        dw, dm, ds = dev(w), dev(mu), dev(sig)
+        assert api.decode_into(cfg, dev(obs.view(np.int16)), dev(ooff), dw, dm, ds, dec) == 0
+        assert np.array_equal(dec.cpu().numpy(), sym)
+        flipped = obs.copy()
+        flipped[ooff[7] + 3] ^= 0x0100
+        ost, osym = orc.decode(ocfg, flipped, ooff, w, mu, sig)
+        gst = api.decode_into(cfg, dev(flipped.view(np.int16)), dev(ooff), dw, dm, ds, dec)
+        assert gst == ost
+        assert np.array_equal(dec.cpu().numpy(), osym)
+    finally:
+        api.set_decode_lanes(0)
+
+
 @pytest.mark.parametrize("lo,hi", [(4194049, 4194304), (-4194304, -4193794)])
 @pytest.mark.parametrize("lanes", [0, 1])
 def test_far_support_bit_exact(api, orc, lo, hi, lanes):
     """Alphabets at the contract's limit |lo|, |hi| <= 2^22 (256 symbols
     ending at 2^22, 511 starting at -2^22; with one lane per stream the
-    straight-line 8- and 9-round searches), means spread over the support:
+    bracketed search), means spread over the support:
     bitstream, offsets and symbols equal the oracle's."""
     rng = np.random.default_rng(abs(lo) % 997 + lanes)
     n, S, K, P = 20000, 64, 3, 16

@@ -1,10 +1,13 @@
 """The decode search's float form of the round decision (Sec. III-A search).
 
-The straight-line decode search carries the interval as the binary32
-boundary b = lo_sym + mid - 1/2 and decides each round with the float test
-y < s1 - b, s1 = slot + 1 + lo_sym - 1/2, where y = RN(F (M - N)) >= 0 and
-the contract's decision is slot >= c_mid = mid + floor(y). This replays the
-arithmetic in numpy binary32 over the ranges the library accepts
+The bracketed decode search's candidate rounds carry the boundary as the
+binary32 value b = lo_sym + mid - 1/2 and decide with the float test
+y < s1 - b, s1 = slot + 1 + lo_sym - 1/2. For y = RN(F (M - N)) >= 0 that
+test is the contract's decision slot >= c_mid = mid + floor(y) (pinned
+here); the candidate rounds feed it an approximate y, and the exact
+confirmation that follows makes the decoded symbol independent of it.
+This replays the arithmetic in numpy binary32 over the ranges the library
+accepts
 (|lo_sym| <= 2^22, N <= 2^15, slot < M <= 2^16):
 - every boundary, s1 and s1 - b is exact;
 - the float test and the integer decision agree, y at, just below and just
