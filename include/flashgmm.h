@@ -251,7 +251,12 @@ int gmm_mlp_adam(int32_t P, float* params, const float* grad, float* m, float* v
  * outside the bitstream, is shorter than two words, is read past its end
  * (missing words read as 0), does not end in the initial state 2^16, or has
  * unread words. The result equals the plain binary search whether or not a
- * bracket is given. stats [device, nullable]. */
+ * bracket is given. With one lane per stream, the A&S kind and 65 to 1,024
+ * symbols and no learned bracket, the search proposes the symbol from the
+ * components' quantiles and an approximate-Phi search and confirms it with
+ * the exact c_j and c_{j+1} (exact binary search where the candidate
+ * fails); c_j being strictly increasing, the symbols are the same.
+ * stats [device, nullable]. */
 int gmm_decode(const gmm_cfg* cfg, int64_t n, const uint16_t* bitstream, int64_t total_words,
                const int64_t* offsets, const float* weights, const float* means,
                const float* scales, int32_t* symbols, const gmm_bracket* bracket,
@@ -364,7 +369,8 @@ int gmm_plan_destroy(gmm_plan* plan);
 
 /* Launch shape of later gmm_decode calls in this process (all threads):
  * lanes = 1 runs one wavefront lane per stream with a binary search
- * (ceil(log2 N) CDF evaluations per symbol); lanes = 2, 4, 8, 16 or 32 lets
+ * (ceil(log2 N) CDF evaluations per symbol, or the bracketed search of
+ * gmm_decode); lanes = 2, 4, 8, 16 or 32 lets
  * that many lanes share a stream and search (lanes+1)-ary, cutting the
  * sequential rounds to ceil(log_{lanes+1} N) at the cost of more total
  * evaluations (for latents with few streams); 0 (default) chooses from the

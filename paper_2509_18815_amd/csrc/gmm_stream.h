@@ -111,10 +111,10 @@ __device__ __forceinline__ int32_t search_loop(const Elem<K>& e, const QCfg& q, 
 //     lies between the smallest and the largest of them, so a rough z(u)
 //     (A&S 26.2.23, |error| < 4.5e-4) and the slot's position u give an
 //     index range [jl, jh] that usually holds j;
-//  2. a binary search over that range with an approximate Phi (A&S 26.2.17
-//     on the hardware reciprocal and exp2, no clamps): its comparisons
-//     differ from the exact ones only where the slot lies within about
-//     1e-6 (M - N) counts of a boundary.
+//  2. a binary search over that range with an approximate Phi (A&S 26.2.16,
+//     |error| < 1e-5, on the hardware reciprocal and exp2, no clamps): its
+//     comparisons differ from the exact ones only where the slot lies
+//     within about 1e-5 (M - N) counts of a boundary.
 // Two exact evaluations then confirm the candidate; a lane whose candidate
 // fails runs the exact binary search (the looped form: it is rare, and one
 // copy keeps the unrolled decode loop small). The wavefront runs as many
@@ -123,7 +123,9 @@ __device__ __forceinline__ int32_t search_loop(const Elem<K>& e, const QCfg& q, 
 // quantiles close together relative to their scales.
 constexpr float kQ23C0 = 2.515517f, kQ23C1 = 0.802853f, kQ23C2 = 0.010328f;
 constexpr float kQ23D1 = 1.432788f, kQ23D2 = 0.189269f, kQ23D3 = 0.001308f;
-constexpr float kAsP = 0.2316419f;
+// A&S 26.2.16: Q(x) = Z(x) (a1 t + a2 t^2 + a3 t^3), t = 1 / (1 + p x)
+constexpr float kA16P = 0.33267f, kA16A1 = 0.4361836f, kA16A2 = -0.1201676f,
+                kA16A3 = 0.9372980f;
 constexpr float kInvSqrt2Pi = 0.3989422804014327f;
 constexpr float kNegHalfLog2e = -0.7213475204444817f;  // -log2(e) / 2
 constexpr float kNeg2Ln2 = -1.3862943611198906f;       // -2 ln 2
@@ -131,15 +133,16 @@ constexpr float kNeg2Ln2 = -1.3862943611198906f;       // -2 ln 2
 // (N > 1024) the looped search serves
 constexpr int kBracketMinRounds = 7, kBracketMaxRounds = 10;
 
-// Approximate Phi(z) - 1/2 (error ~1e-7): the A&S 26.2.17 tail with the
-// hardware reciprocal and exp2.
+// Approximate Phi(z) - 1/2 (|error| ~1e-5): the A&S 26.2.16 tail with the
+// hardware reciprocal and exp2. (The five-term 26.2.17, error ~1e-7, costs
+// two more instructions per component, which its rarer fallbacks do not
+// repay: 4K decode 254 against 250 us, 256-latent plan 12.9 against
+// 12.2 ms.)
 __device__ __forceinline__ float approx_half(float z) {
   const float x = __builtin_fabsf(z);
-  const float t = __builtin_amdgcn_rcpf(fma32(x, kAsP, 1.0f));
-  float h = fma32(kAsB5 * kInvSqrt2Pi, t, kAsB4 * kInvSqrt2Pi);
-  h = fma32(h, t, kAsB3 * kInvSqrt2Pi);
-  h = fma32(h, t, kAsB2 * kInvSqrt2Pi);
-  h = fma32(h, t, kAsB1 * kInvSqrt2Pi);
+  const float t = __builtin_amdgcn_rcpf(fma32(x, kA16P, 1.0f));
+  float h = fma32(kA16A3 * kInvSqrt2Pi, t, kA16A2 * kInvSqrt2Pi);
+  h = fma32(h, t, kA16A1 * kInvSqrt2Pi);
   const float g = __builtin_amdgcn_exp2f((z * z) * kNegHalfLog2e);
   return __builtin_copysignf(fma32(-g, h * t, 0.5f), z);
 }
