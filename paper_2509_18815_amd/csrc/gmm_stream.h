@@ -127,7 +127,9 @@ constexpr float kQ23D1 = 1.432788f, kQ23D2 = 0.189269f, kQ23D3 = 0.001308f;
 constexpr float kA16P = 0.33267f, kA16A1 = 0.4361836f, kA16A2 = -0.1201676f,
                 kA16A3 = 0.9372980f;
 constexpr float kInvSqrt2Pi = 0.3989422804014327f;
-constexpr float kNegHalfLog2e = -0.7213475204444817f;  // -log2(e) / 2
+// z is carried pre-scaled by kappa = sqrt(log2(e) / 2), so that the
+// density factor exp(-z^2 / 2) is exp2(-(kappa z)^2)
+constexpr float kKappa = 0.8493218002880191f;
 constexpr float kNeg2Ln2 = -1.3862943611198906f;       // -2 ln 2
 // below 7 exact rounds (N <= 64) the plain search is as cheap; above 10
 // (N > 1024) the looped search serves
@@ -138,13 +140,13 @@ constexpr int kBracketMinRounds = 7, kBracketMaxRounds = 10;
 // two more instructions per component, which its rarer fallbacks do not
 // repay: 4K decode 254 against 250 us, 256-latent plan 12.9 against
 // 12.2 ms.)
-__device__ __forceinline__ float approx_half(float z) {
-  const float x = __builtin_fabsf(z);
-  const float t = __builtin_amdgcn_rcpf(fma32(x, kA16P, 1.0f));
+__device__ __forceinline__ float approx_half(float zk) {  // zk = kappa z
+  const float x = __builtin_fabsf(zk);
+  const float t = __builtin_amdgcn_rcpf(fma32(x, kA16P / kKappa, 1.0f));
   float h = fma32(kA16A3 * kInvSqrt2Pi, t, kA16A2 * kInvSqrt2Pi);
   h = fma32(h, t, kA16A1 * kInvSqrt2Pi);
-  const float g = __builtin_amdgcn_exp2f((z * z) * kNegHalfLog2e);
-  return __builtin_copysignf(fma32(-g, h * t, 0.5f), z);
+  const float g = __builtin_amdgcn_exp2f(-(zk * zk));
+  return __builtin_copysignf(fma32(-g, h * t, 0.5f), zk);
 }
 
 // Maximum / minimum over the 16 lanes of a DPP row (every lane receives
@@ -209,23 +211,28 @@ __device__ __forceinline__ int32_t search_bracketed(const Elem<K>& e, const QCfg
   const int32_t rl = (wd <= 0) ? 0 : 32 - __builtin_clz((uint32_t)wd);
   const int32_t rw = min(wave_max_small(rl), rounds);
   // 2. approximate binary search over [jl, jh]
-  float ws[K], zo[K];
+  // the boundaries as floats b = j + lo - 1/2 (exact: integers and
+  // half-integers below 2^23), so a round costs no conversions
+  float ws[K], zr[K], zo[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     ws[k] = e.w[k] * q.span;
-    zo[k] = -e.mu[k] * e.r[k];
+    zr[k] = e.r[k] * kKappa;
+    zo[k] = -e.mu[k] * zr[k];
   }
   const float h0 = e.hw * q.span;
   const float s1 = (float)(slot + 1u) + q.lo_mh;
-  int32_t j = jl;
+  const float bh = (float)jh + q.lo_mh;
+  float bj = (float)jl + q.lo_mh;
   for (int i = rw - 1; i >= 0; --i) {
-    const int32_t mid = j + (1 << i);
-    const float b = (float)min(mid, N - 1) + q.lo_mh;
+    const float bm = bj + (float)(1 << i);
+    const float b = __builtin_fminf(bm, bh);
     float y = h0;
 #pragma unroll
-    for (int k = 0; k < K; ++k) y = fma32(ws[k], approx_half(fma32(b, e.r[k], zo[k])), y);
-    j = (mid <= jh && y < s1 - b) ? mid : j;
+    for (int k = 0; k < K; ++k) y = fma32(ws[k], approx_half(fma32(b, zr[k], zo[k])), y);
+    bj = (bm <= bh && y < s1 - b) ? bm : bj;
   }
+  const int32_t j = (int32_t)(bj - q.lo_mh);
   // 3. confirm with the exact c_j and c_{j+1}
   const uint32_t cl = cdf_at<K, 0, kFast>(e, q, j);
   const uint32_t ch = cdf_at<K, 0, kFast>(e, q, j + 1);
