@@ -10,6 +10,8 @@ K = 5 mixture components, support [-511, 511] (N = 1023), P = 16.
   each, the stream-count rule of the batch): autotuned plans, round trip
   through the plain and the bracket decode, and sampled streams of every
   latent re-encoded and decoded by the oracle one by one.
+- Edge-of-range parameters with uniform symbols (K = 3, N = 256 and K = 5,
+  N = 1023): every decode candidate returns the oracle-encoded symbols.
 """
 import numpy as np
 import pytest
@@ -191,3 +193,36 @@ def test_k5_full_size_latents_sampled_streams(api, orc, brief_model):
     for p in (pe, pd, pb):
         p.close()
     br.close()
+
+
+@pytest.mark.parametrize("k,lo,hi", [(3, -128, 127), (5, -511, 511)])
+def test_plans_adversarial_params_every_candidate(api, orc, k, lo, hi):
+    """Batched decode plans on edge-of-range parameters (tiny and huge
+    scales, zero and denormal weights, far means, means on boundaries) with
+    symbols spread uniformly over the support, so that one-lane candidates
+    from the bracketed search fail often and take the exact fallback: every
+    decode candidate returns the oracle-encoded symbols."""
+    rng = np.random.default_rng(hi - lo + k)
+    lats = []
+    for n, S in [(1, 1), (777, 64), (5003, 128), (12000, 256)]:
+        w, mu, sig = synth.adversarial_params(rng, n, k)
+        sym = rng.integers(lo, hi + 1, size=n).astype(np.int32)
+        st, obs, ooff = orc.encode(orc.make_cfg(k, lo, hi, P, S), sym, w, mu, sig)
+        assert st == orc.OK
+        lats.append({"n": n, "S": S, "sym": sym, "d": [dev(x) for x in (w, mu, sig)],
+                     "bs": dev(obs.view(np.int16)), "off": dev(ooff)})
+    dio = [{"weights": L["d"][0], "means": L["d"][1], "scales": L["d"][2],
+            "bitstream": L["bs"], "words": int(L["off"][-1].item()), "offsets": L["off"],
+            "decoded": torch.empty(L["n"], dtype=torch.int32, device="cuda")} for L in lats]
+    pd = api.Plan(k, lo, hi, P, [L["n"] for L in lats], [L["S"] for L in lats], op=1,
+                  autotune=False)
+    try:
+        for cand in pd.candidates():
+            pd.set_config(*cand)
+            for d in dio:
+                d["decoded"].fill_(-1)
+            assert pd.run(dio) == api.OK, cand
+            for b, (d, L) in enumerate(zip(dio, lats)):
+                assert np.array_equal(d["decoded"].cpu().numpy(), L["sym"]), (cand, b)
+    finally:
+        pd.close()
