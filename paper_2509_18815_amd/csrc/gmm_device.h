@@ -331,7 +331,7 @@ __device__ __forceinline__ Elem<K> make_elem(const QCfg& q, const float (&rw)[K]
     w[k] = rw[k];
     sc[k] = rs[k];
   }
-  if (q.raw) raw_to_params<K>(w, sc);
+  if (__builtin_expect(q.raw != 0, 0)) raw_to_params<K>(w, sc);
   Elem<K> e;
 #pragma unroll
   for (int k = 0; k < K; ++k) {

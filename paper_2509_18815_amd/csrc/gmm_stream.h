@@ -236,7 +236,7 @@ __device__ __forceinline__ int32_t search_bracketed(const Elem<K>& e, const QCfg
   // 3. confirm with the exact c_j and c_{j+1}
   const uint32_t cl = cdf_at<K, 0, kFast>(e, q, j);
   const uint32_t ch = cdf_at<K, 0, kFast>(e, q, j + 1);
-  if (cl <= slot && slot < ch) {
+  if (__builtin_expect(cl <= slot && slot < ch, 1)) {
     c_lo = cl;
     c_hi = ch;
     return j;
@@ -253,7 +253,7 @@ __device__ __forceinline__ int32_t search_bs(const Elem<K>& e, const QCfg& q, in
                                              int nfree, uint32_t slot, uint32_t& c_lo,
                                              uint32_t& c_hi) {
   if constexpr (kKind == 0 && kBracket) {
-    if (rounds >= kBracketMinRounds && rounds <= kBracketMaxRounds)
+    if (__builtin_expect(rounds >= kBracketMinRounds && rounds <= kBracketMaxRounds, 1))
       return search_bracketed<K, kFast>(e, q, rounds, nfree, slot, c_lo, c_hi);
   }
   return search_loop<K, kKind, kFast>(e, q, rounds, nfree, slot, c_lo, c_hi);
