@@ -92,7 +92,7 @@ __global__ void __launch_bounds__(256)
   const int g = (int)(gt % L);
   // groups never straddle the S boundary (S * L lanes, L divides 64)
   if (s < S) {
-    const bool bad = decode_stream<K, kKind, kFast, L, kGather, L == 1, kBuf>(
+    const bool bad = decode_stream<K, kKind, kFast, L, kGather, L == 1, kBuf, kBuf ? 4 : 3>(
         q, P, rounds, n, S, s, g, bs, total_words, offsets, w, mu, sg, sym, idx, n_total);
     if (bad && g == 0) atomicOr(status, kStCorrupt);
   }

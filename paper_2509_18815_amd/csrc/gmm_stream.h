@@ -800,7 +800,8 @@ __device__ __forceinline__ float opaque_copy(float v) {
 // With kGather the coded sequence is the subset idx[0..n) of a latent of
 // n_total elements: pass position i reads its parameters at element idx[i]
 // of the [K][n_total] planes and writes its symbol to sym[idx[i]].
-// kBracket selects the bracketed search for one lane per stream (search_bs).
+// kBracket selects the bracketed search for one lane per stream (search_bs);
+// kRing1 the depth of the parameter ring with one lane per stream.
 // With kBuf the parameters, the refill words and the symbols go through
 // buffer resources with 32-bit byte offsets: one offset per step for all
 // 3K parameter loads (the plane rows at constant scalar offsets k n 4), no
@@ -808,7 +809,7 @@ __device__ __forceinline__ float opaque_copy(float v) {
 // the bitstream reads 0 by the resource's range check). The caller selects
 // it only when every offset fits: buffer_offsets_fit below.
 template <int K, int kKind, bool kFast, int L, bool kGather = false, bool kBracket = false,
-          bool kBuf = false>
+          bool kBuf = false, int kRing1 = 3>
 __device__ __forceinline__ bool decode_stream(const QCfg& q, int P, int rounds, int64_t n,
                                               int64_t S, int64_t s, int g,
                                               const uint16_t* __restrict__ bs, int64_t total_words,
@@ -845,7 +846,12 @@ __device__ __forceinline__ bool decode_stream(const QCfg& q, int P, int rounds, 
   // parameters get kRing - 1 whole steps to arrive. Every load is
   // unconditional (positions past the end reload the last element or word)
   // so the number of loads per step is fixed and the wait counts stay exact.
-  constexpr int kRing = (L == 1) ? 3 : 2;
+  // kRing1 is the depth with one lane per stream: 4 for the whole-latent
+  // decode on buffer resources (4K decode 244.9 -> 236.3 us alternated on
+  // one box; 2, 5 and 6 steps 248.6, 236.6 and 235.4 us), 3 elsewhere
+  // (the batched kernels, which share SIMDs among several wavefronts, lost
+  // on the 256-latent plan with 4: 11.71 -> 11.99 ms).
+  constexpr int kRing = (L == 1) ? kRing1 : 2;
   const int64_t last = ns - 1;
   static_assert(!(kBuf && kGather), "the buffer path reads the planes in stream order");
   [[maybe_unused]] __amdgpu_buffer_rsrc_t bw_, bm_, bsg_, bbs_, bsym_;
