@@ -192,6 +192,30 @@ def test_bracketed_search_bit_exact(api, orc, lo, hi):
         api.set_decode_lanes(0)
 
 
+@pytest.mark.parametrize("n,S", [(300, 512), (513, 512), (64, 64), (1, 64)])
+def test_bracketed_search_sparse_streams(api, orc, n, S):
+    """The bracketed search (one lane per stream, N = 511) when wavefronts
+    hold empty streams, one-symbol streams and ragged tails (lanes that
+    are not live take part in the wavefront's round count): symbols equal
+    the oracle's."""
+    rng = np.random.default_rng(n * 7 + S)
+    K, lo, hi = 3, -255, 255
+    w, mu, sig = synth.random_params(rng, n, K)
+    sym = np.clip(np.rint(mu[0] + sig[0] * rng.normal(size=n)), lo, hi).astype(np.int32)
+    ocfg = orc.make_cfg(K, lo, hi, 16, S, 0)
+    st, obs, ooff = orc.encode(ocfg, sym, w, mu, sig)
+    assert st == orc.OK
+    cfg = api.make_cfg(K, lo, hi, 16, S, 0)
+    api.set_decode_lanes(1)
+    try:
+        dec = torch.empty(n, dtype=torch.int32, device="cuda")
+        assert api.decode_into(cfg, dev(obs.view(np.int16)), dev(ooff), dev(w), dev(mu),
+                               dev(sig), dec) == 0
+        assert np.array_equal(dec.cpu().numpy(), sym)
+    finally:
+        api.set_decode_lanes(0)
+
+
 @pytest.mark.parametrize("lo,hi", [(4194049, 4194304), (-4194304, -4193794)])
 @pytest.mark.parametrize("lanes", [0, 1])
 def test_far_support_bit_exact(api, orc, lo, hi, lanes):
