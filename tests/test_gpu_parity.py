@@ -192,6 +192,32 @@ def test_bracketed_search_bit_exact(api, orc, lo, hi):
         api.set_decode_lanes(0)
 
 
+@pytest.mark.parametrize("P,lo,hi", [(11, -511, 511), (12, -255, 255), (11, 0, 1023)])
+def test_bracketed_search_small_precision(api, orc, P, lo, hi):
+    """The bracketed search with M - N small against N (P = 11 with 1,023
+    and 1,024 symbols, P = 12 with 511): the slot's position u then ranges
+    beyond [0, 1] and many symbols have frequency 1. Symbols spread over
+    the support decode to the oracle's."""
+    rng = np.random.default_rng(P * 1000 + hi - lo)
+    n, S, K = 20011, 256, 3
+    w, mu, sig = synth.random_params(rng, n, K)
+    centre = np.float32((lo + hi) / 2)
+    mu = np.ascontiguousarray((mu * np.float32(30.0) + centre).astype(np.float32))
+    sym = rng.integers(lo, hi + 1, size=n).astype(np.int32)
+    ocfg = orc.make_cfg(K, lo, hi, P, S, 0)
+    st, obs, ooff = orc.encode(ocfg, sym, w, mu, sig)
+    assert st == orc.OK
+    cfg = api.make_cfg(K, lo, hi, P, S, 0)
+    api.set_decode_lanes(1)
+    try:
+        dec = torch.empty(n, dtype=torch.int32, device="cuda")
+        assert api.decode_into(cfg, dev(obs.view(np.int16)), dev(ooff), dev(w), dev(mu),
+                               dev(sig), dec) == 0
+        assert np.array_equal(dec.cpu().numpy(), sym)
+    finally:
+        api.set_decode_lanes(0)
+
+
 @pytest.mark.parametrize("n,S", [(300, 512), (513, 512), (64, 64), (1, 64)])
 def test_bracketed_search_sparse_streams(api, orc, n, S):
     """The bracketed search (one lane per stream, N = 511) when wavefronts
