@@ -201,14 +201,16 @@ __device__ __forceinline__ int32_t search_bracketed(const Elem<K>& e, const QCfg
     qmin = __builtin_fminf(qmin, v);
     qmax = __builtin_fmaxf(qmax, v);
   }
-  // symbol index of a value v: floor(v - (lo - 1/2)); one index of margin
+  // symbol index of a value v: floor(v - (lo - 1/2)); one index of margin.
+  // The indices stay floats (integers below 2^23, exact); the rounds the
+  // lane needs are the bit length of jh - jl, the exponent of its frexp
+  // (0 for 0).
   const float fN1 = (float)(N - 1);
-  const int32_t jl = (int32_t)__builtin_fminf(
+  const float jl = __builtin_fminf(
       __builtin_fmaxf(__builtin_floorf(qmin - q.lo_mh) - 1.0f, 0.0f), fN1);
-  const int32_t jh = (int32_t)__builtin_fminf(
-      __builtin_fmaxf(__builtin_floorf(qmax - q.lo_mh) + 1.0f, (float)jl), fN1);
-  const int32_t wd = jh - jl;  // width - 1
-  const int32_t rl = (wd <= 0) ? 0 : 32 - __builtin_clz((uint32_t)wd);
+  const float jh = __builtin_fminf(
+      __builtin_fmaxf(__builtin_floorf(qmax - q.lo_mh) + 1.0f, jl), fN1);
+  const int32_t rl = __builtin_amdgcn_frexp_expf(jh - jl);
   const int32_t rw = min(wave_max_small(rl), rounds);
   // 2. approximate binary search over [jl, jh]
   // the boundaries as floats b = j + lo - 1/2 (exact: integers and
@@ -222,8 +224,8 @@ __device__ __forceinline__ int32_t search_bracketed(const Elem<K>& e, const QCfg
   }
   const float h0 = e.hw * q.span;
   const float s1 = (float)(slot + 1u) + q.lo_mh;
-  const float bh = (float)jh + q.lo_mh;
-  float bj = (float)jl + q.lo_mh;
+  const float bh = jh + q.lo_mh;
+  float bj = jl + q.lo_mh;
   for (int i = rw - 1; i >= 0; --i) {
     const float bm = bj + (float)(1 << i);
     const float b = __builtin_fminf(bm, bh);
