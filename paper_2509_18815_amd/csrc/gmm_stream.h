@@ -235,9 +235,13 @@ __device__ __forceinline__ int32_t search_bracketed(const Elem<K>& e, const QCfg
     bj = (bm <= bh && y < s1 - b) ? bm : bj;
   }
   const int32_t j = (int32_t)(bj - q.lo_mh);
-  // 3. confirm with the exact c_j and c_{j+1}
-  const uint32_t cl = cdf_at<K, 0, kFast>(e, q, j);
-  const uint32_t ch = cdf_at<K, 0, kFast>(e, q, j + 1);
+  // 3. confirm with the exact c_j and c_{j+1} (cdf_inner's values: bj is
+  // exactly j + lo - 1/2 and bj + 1 the next boundary; j < N, so only c_0
+  // and c_N need their ends)
+  const float y0 = cdf_scaled<K, 0, kFast>(e, q, bj);
+  const float y1 = cdf_scaled<K, 0, kFast>(e, q, bj + 1.0f);
+  const uint32_t cl = (j <= 0) ? 0u : (uint32_t)j + (uint32_t)y0;
+  const uint32_t ch = (j + 1 >= N) ? q.M : (uint32_t)(j + 1) + (uint32_t)y1;
   if (__builtin_expect(cl <= slot && slot < ch, 1)) {
     c_lo = cl;
     c_hi = ch;
