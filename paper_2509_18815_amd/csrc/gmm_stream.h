@@ -227,12 +227,13 @@ __device__ __forceinline__ int32_t search_bracketed(const Elem<K>& e, const QCfg
   const float bh = jh + q.lo_mh;
   float bj = jl + q.lo_mh;
   for (int i = rw - 1; i >= 0; --i) {
-    const float bm = bj + (float)(1 << i);
-    const float b = __builtin_fminf(bm, bh);
+    // 2^i as float bits built on the scalar unit; a midpoint past jh is
+    // evaluated anyway (the approximation needs no range) and not taken
+    const float b = bj + __builtin_bit_cast(float, (uint32_t)(127 + i) << 23);
     float y = h0;
 #pragma unroll
     for (int k = 0; k < K; ++k) y = fma32(ws[k], approx_half(fma32(b, zr[k], zo[k])), y);
-    bj = (bm <= bh && y < s1 - b) ? bm : bj;
+    bj = (b <= bh && y < s1 - b) ? b : bj;
   }
   const int32_t j = (int32_t)(bj - q.lo_mh);
   // 3. confirm with the exact c_j and c_{j+1} (cdf_inner's values: bj is
